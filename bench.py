@@ -1,0 +1,225 @@
+"""Benchmark of the anisotropic 3PCF estimator on one MI355X.
+
+Workload (default): the batched covariance run -- 64 clustered catalogues
+(Zel'dovich + RSD, sizes log-uniform in [5e4, 3e5], 1000 Mpc/h periodic boxes,
+per-catalogue seeds), 10 radial bins over [20, 120] Mpc/h, lmax = 10, every
+multipole with L <= 2, processed by one tpcf_run_catalogs call per step with
+the positions already resident in HBM. The same step is timed for the mixed
+path (FP32 pair pass + split-BF16 contraction) and for the plain FP64 path.
+
+Prints ONE JSON line. `value` is pairs/s into a_lm(r) (ordered in-shell pairs
+of all catalogues per step / seconds per step) for the mixed path.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pairs/s into a_lm(r) + catalogs/hour, batched mixed vs plain FP64, 1 GPU"
+PEAK_FP32_VALU = 157.3e12   # MI355X published FP32 vector peak (packed)
+PEAK_BF16_MFMA = 2.5e15     # dense
+PEAK_HBM = 8.0e12
+
+
+def flop_per_pair(lmax: int) -> int:
+    """Algorithmic FP32 work per in-shell pair of the harmonic pass:
+    F(lmax) = 7 N_lm + 6 lmax + 40 with N_lm = (lmax+1)(lmax+2)/2 (three flops
+    of recurrence, two of phase scaling and two of accumulation per
+    coefficient, plus separation, normalisation, bin and powers)."""
+    nlm = (lmax + 1) * (lmax + 2) // 2
+    return 7 * nlm + 6 * lmax + 40
+
+
+def contraction_flop(sizes, nb, lmax):
+    """Dense MFMA work of the contraction, sum over catalogues and m of
+    2 K_rows K_m^2 (K_rows = P for m = 0, 2P for m >= 1, K_m = nb (lmax-m+1))."""
+    tot = 0.0
+    for P in sizes:
+        for m in range(lmax + 1):
+            K = nb * (lmax - m + 1)
+            tot += 2.0 * (P if m == 0 else 2 * P) * K * K
+    return tot
+
+
+def all_multipoles(lmax, Lmax):
+    out = []
+    for l1 in range(lmax + 1):
+        for l2 in range(lmax + 1):
+            for L in range(abs(l1 - l2), min(l1 + l2, Lmax) + 1):
+                if (l1 + l2 + L) % 2 == 0:
+                    out.append((l1, l2, L))
+    return out
+
+
+def make_batch(torch, ncat, lo, hi, box, sigma, f, grid, device):
+    from paper_2408_03036_amd import catalogs as C
+    sizes = C.log_uniform_sizes(ncat, lo, hi, C.BASE_SEED + 777)
+    cats = [C.zeldovich_torch(int(n), box, sigma, f, C.catalogue_seed(i), grid=grid, device=device)
+            for i, n in enumerate(sizes)]
+    pos = torch.cat(cats, dim=0).contiguous()
+    torch.cuda.synchronize()
+    return sizes, pos
+
+
+def time_steps(torch, h, sizes, pos, mults, steps, warmup):
+    for _ in range(warmup):
+        h.run_catalogs(sizes, sizes, pos, None, mults)
+    h.sync()
+    h.stage_times()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = h.run_catalogs(sizes, sizes, pos, None, mults)
+    h.sync()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ms, nl = h.stage_times()
+    npairs = h.pair_count()
+    return dt, ms, nl, npairs, out
+
+
+def cpu_baseline(pos_np, box, edges, lmax, target_s=15.0):
+    """Times the FP64 CPU oracle on a bounded sample of primaries of one
+    catalogue (all host threads), scaled to pairs/s."""
+    from oracle import oracle as O
+    nthr = os.cpu_count() or 1
+    try:
+        nthr = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    nthr = min(nthr, 16)
+    n = pos_np.shape[0]
+    probe = min(n, 256)
+    t0 = time.perf_counter()
+    r = O.estimate(pos_np, box, edges, lmax, prim_first=0, prim_count=probe, nthreads=nthr)
+    t1 = time.perf_counter() - t0
+    rate = r.npairs / max(t1, 1e-9)
+    per_prim = r.npairs / probe
+    count = int(min(n, max(probe, target_s * rate / max(per_prim, 1.0))))
+    t0 = time.perf_counter()
+    r = O.estimate(pos_np, box, edges, lmax, prim_first=0, prim_count=count, nthreads=nthr)
+    t1 = time.perf_counter() - t0
+    return {"value": r.npairs / t1, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{count} primaries of catalogue 0 ({r.npairs} pairs, full estimator incl. "
+                      f"NNN accumulation) in {t1:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ncat", type=int, default=64)
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "fp32", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--refine", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the catalogue batch would be split across GPUs by whole catalogues).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2408_03036_amd import tpcf as T
+
+    dev = "cuda:0"
+    box, sigma, fgrowth, grid = 1000.0, 6.0, 0.8, 256
+    edges = np.linspace(20.0, 120.0, 11)
+    lmax, Lmax = 10, 2
+    mults = all_multipoles(lmax, Lmax)
+    print(f"[bench] generating {args.ncat} catalogues on the GPU", file=sys.stderr, flush=True)
+    sizes, pos = make_batch(torch, args.ncat, 50_000, 300_000, box, sigma, fgrowth, grid, dev)
+    ntot = int(sizes.sum())
+    prec_id = {"bf16x3": T.PREC_MIXED_BF16X3, "bf16x6": T.PREC_MIXED_BF16X6,
+               "fp32": T.PREC_FP32, "fp64": T.PREC_FP64}[args.precision]
+
+    print(f"[bench] {args.precision}: {args.warmup} warmup + {args.steps} timed steps",
+          file=sys.stderr, flush=True)
+    h = T.Handle(box, edges, lmax, precision=prec_id, grid_refine=args.refine,
+                 workspace_limit=96 << 30)
+    h.set_timing(True)
+    dt, ms, nl, npairs, out = time_steps(torch, h, sizes, pos, mults, args.steps, args.warmup)
+    h.close()
+    value = npairs / dt
+    cats_per_hour = args.ncat * 3600.0 / dt
+
+    # dominant kernel: the harmonic pass (stage 2)
+    t_alm = ms[2] / max(nl[2], 1) / 1e3
+    launches_per_step = nl[2] / args.steps
+    flop_launch = npairs * flop_per_pair(lmax) / launches_per_step
+    achieved = flop_launch / t_alm
+    roof = {"kernel": "k_pair_alm<float,10> (harmonic pass)", "bound": "alu",
+            "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+            "flop_per_pair": flop_per_pair(lmax), "avg_launch_ms": t_alm * 1e3}
+    stages = {"grid_ms": ms[0] / args.steps, "pair_bin_ms": ms[1] / args.steps,
+              "pair_alm_ms": ms[2] / args.steps, "contract_ms": ms[3] / args.steps,
+              "finalize_ms": ms[4] / args.steps}
+    cflop = contraction_flop(sizes, len(edges) - 1, lmax)
+    mfma_mult = {T.PREC_MIXED_BF16X3: 3, T.PREC_MIXED_BF16X6: 6}.get(prec_id, 1)
+    contraction = {"dense_flop": cflop, "ms": stages["contract_ms"],
+                   "tflops_fp32_equiv": cflop / (stages["contract_ms"] / 1e3) / 1e12
+                   if stages["contract_ms"] > 0 else None,
+                   "mfma_products_per_fp32_product": mfma_mult}
+    if prec_id in (T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6) and stages["contract_ms"] > 0:
+        contraction["frac_bf16_peak"] = cflop * mfma_mult / (stages["contract_ms"] / 1e3) / PEAK_BF16_MFMA
+
+    fp64 = None
+    if not args.no_fp64 and prec_id != T.PREC_FP64:
+        print("[bench] fp64 comparison", file=sys.stderr, flush=True)
+        h = T.Handle(box, edges, lmax, precision=T.PREC_FP64, grid_refine=args.refine,
+                     workspace_limit=96 << 30)
+        h.set_timing(True)
+        dt64, ms64, nl64, np64, out64 = time_steps(torch, h, sizes, pos, mults, max(2, args.steps // 2), 1)
+        h.close()
+        ref = out64.abs().max().item()
+        err = (out - out64).abs().max().item() / ref
+        fp64 = {"value": np64 / dt64, "unit": "pairs/s", "ms_per_step": dt64 * 1e3,
+                "catalogs_per_hour": args.ncat * 3600.0 / dt64,
+                "pair_alm_ms": ms64[2] / max(2, args.steps // 2),
+                "contract_ms": ms64[3] / max(2, args.steps // 2),
+                "speedup_mixed_vs_fp64": dt64 / dt,
+                "mixed_rel_err_vs_fp64_path": err, "pairs_equal": int(np64) == int(npairs)}
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        n0 = int(sizes[0])
+        cpu = cpu_baseline(pos[:n0].cpu().numpy(), box, edges, lmax)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec_id != T.PREC_FP64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched covariance run: {args.ncat} Zel'dovich+RSD catalogues, "
+                               f"sizes log-uniform [5e4,3e5] ({ntot} points), 1000 Mpc/h boxes, "
+                               f"10 bins [20,120] Mpc/h, lmax 10, L<=2 ({len(mults)} multipoles)",
+                   "precision": args.precision, "ncat": args.ncat, "points": ntot,
+                   "pairs_per_step": int(npairs), "parallelism": "single GPU"},
+        "catalogs_per_hour": cats_per_hour,
+        "stages_ms": stages,
+        "roofline": roof,
+        "contraction": contraction,
+        "fp64_path": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

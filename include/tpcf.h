@@ -1,0 +1,180 @@
+/*
+ * tpcf.h -- C ABI of libtpcf.so: the anisotropic three-point correlation
+ * function (3PCF) estimator of arXiv:2408.03036, Sec. 4.2, on one MI355X.
+ *
+ * The library computes, for a periodic box of side L with points x_i and
+ * weights w_i (1 for data; -N_D/N_R for randoms in the data-minus-randoms
+ * field of the Szapudi-Szalay estimator, eq. (ssest)):
+ *
+ *   a_lm(p, b)  = sum over neighbours j of p with |x_j - x_p| in radial bin b
+ *                 of w_j conj(Y_lm(rhat_pj))                            eq. (alm)
+ *   NNN^m_{l1 l2}(b1, b2) = sum_p w_p [a_{l1 m}(p,b1) conj(a_{l2 m}(p,b2))
+ *                 - delta_{b1 b2} sum_j w_j^2 conj(Y_{l1 m}) Y_{l2 m}]
+ *                 (m = m' because the line of sight is the fixed z axis;
+ *                  eq. (measured_mult) averaged over positions x)
+ *   zeta_{l1 l2 L}(b1, b2) = 4 pi sqrt((2l1+1)(2l2+1)) (2L+1) H_{l1 l2 L}
+ *                 sum_m (l1 l2 L; m -m 0) (-1)^m NNN^m / RRR(b1, b2)
+ *                 (eq. (slep2sugy), normalised as the coefficient of the
+ *                  tripolar basis of eq. (TSHbasis)), with the analytic
+ *                 periodic-box random-triplet count
+ *                 RRR = N_D (N_D-1)(N_D-2) V_b1 V_b2 / L^6.
+ * Y_lm is orthonormal; bins are half-open [e_b, e_{b+1}); the minimum-image
+ * separation is used; pairs at zero separation and degenerate triangles
+ * (j == k) are excluded.
+ *
+ * Conventions for every call:
+ *  - Pointers prefixed d_ are DEVICE pointers on the handle's device (for
+ *    example torch.Tensor.data_ptr()); h_ are HOST pointers. The caller owns
+ *    every buffer it passes; the library owns its workspace.
+ *  - Work is enqueued on the HIP stream given to tpcf_create; device outputs
+ *    are valid once that stream has reached them (tpcf_sync waits for it).
+ *  - Every call returns a tpcf_status; no C++ exception crosses the ABI.
+ *    Arguments are validated before any device work is enqueued.
+ *    tpcf_last_error() gives a message for the last failing call.
+ *  - A handle is used by one host thread at a time.
+ *  - Lengths are in the units of `box` (Mpc/h in the paper).
+ */
+#ifndef TPCF_H
+#define TPCF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpcf_handle_s* tpcf_handle;
+
+typedef enum {
+    TPCF_OK = 0,
+    TPCF_ERR_ARG = -1,     /* invalid argument (NULL pointer, bad size, bad triple) */
+    TPCF_ERR_RANGE = -2,   /* configuration outside the supported range              */
+    TPCF_ERR_ALLOC = -3,   /* device memory could not be obtained or over budget     */
+    TPCF_ERR_DEVICE = -4,  /* a HIP call failed, or non-finite input positions       */
+    TPCF_ERR_STATE = -5    /* call out of order (e.g. contract before accumulate)    */
+} tpcf_status;
+
+/* Arithmetic of the pair pass and of the contraction. */
+typedef enum {
+    TPCF_PREC_FP64 = 0,         /* FP64 pair pass, FP64 MFMA contraction                      */
+    TPCF_PREC_FP32 = 1,         /* FP32 pair pass, FP32 MFMA contraction, FP64 final sums     */
+    TPCF_PREC_MIXED_BF16X3 = 2, /* FP32 pair pass, split-BF16 contraction: x = hi + lo (BF16),
+                                   products hi.hi + hi.lo + lo.hi on BF16 MFMA, FP32
+                                   accumulation per subchunk, FP64 final sums                 */
+    TPCF_PREC_MIXED_BF16X6 = 3  /* as above with x = hi + mid + lo and six products (every
+                                   product above 2^-24 relative): FP32-level accuracy for
+                                   sparse bins at twice the BF16 MFMA work                    */
+} tpcf_precision;
+
+enum {
+    TPCF_F_KEEP_DEGENERATE = 1u, /* keep j == k terms (default: distinct triplets only)     */
+    TPCF_F_PAPER_LITERAL = 2u    /* output eq. (slep2sugy) exactly as printed, applied to the
+                                    orthonormal-Y coefficients (4 pi)^2 NNN^m / RRR; equals the
+                                    default output times 4 pi / sqrt((2l1+1)(2l2+1))          */
+};
+
+typedef struct {
+    double box;              /* L > 0, finite; the box is periodic in x, y and z             */
+    int32_t nbins;           /* 1 .. 32 radial bins                                           */
+    const double* h_edges;   /* nbins+1 strictly increasing edges, edges[0] >= 0,
+                                edges[nbins] <= box/2 (minimum image); copied at create       */
+    int32_t lmax;            /* 0 .. 12                                                       */
+    int32_t precision;       /* tpcf_precision                                                */
+    uint32_t flags;          /* TPCF_F_* bits                                                 */
+    int32_t grid_refine;     /* cells per r_max along an axis for the neighbour grid,
+                                1 .. 4; 0 = automatic                                         */
+    int64_t workspace_limit; /* device bytes the handle may hold; 0 = 64 GiB                  */
+} tpcf_config;
+
+/* Creates a handle bound to `device` (HIP ordinal) and `hip_stream`
+ * (a hipStream_t, or NULL for the null stream). Copies *cfg. */
+tpcf_status tpcf_create(const tpcf_config* cfg, int device, void* hip_stream, tpcf_handle* out);
+
+/* Releases the handle and its device workspace (waits for its stream). NULL is a no-op. */
+void tpcf_destroy(tpcf_handle h);
+
+/* Message of the last failing call on h (static string for h == NULL); never NULL. */
+const char* tpcf_last_error(tpcf_handle h);
+
+/*
+ * Step 1 -- neighbour grid (the linked-list partition of Sec. 4.1, built as a
+ * counting sort of the points by cell).
+ *  d_pos : n x 3 float64, row-major; positions are wrapped into [0, box).
+ *  d_w   : n float64 weights, or NULL for all ones.
+ *  n     : number of points (every point is also a primary), 1 .. 2^27.
+ *  n_data: N_D used in RRR (the number of data points), >= 3.
+ * The buffers must stay valid until tpcf_alm_accumulate has been enqueued.
+ * Non-finite positions make the next call return TPCF_ERR_DEVICE.
+ */
+tpcf_status tpcf_build_grid(tpcf_handle h, const double* d_pos, const double* d_w,
+                            int64_t n, int64_t n_data);
+
+/*
+ * Step 2 -- pair pass: for every primary, every neighbour in the shells;
+ * accumulates a_lm(p, b) (eq. (alm)) and the degenerate-triangle moments
+ * sum_j w_j^2 P_L(cos theta_pj), L <= 2 lmax. Requires tpcf_build_grid.
+ */
+tpcf_status tpcf_alm_accumulate(tpcf_handle h);
+
+/*
+ * Copies a_lm(p, b) = sum_j w_j conj(Y_lm(rhat_pj)) of primaries
+ * [first, first+count) (indices into the d_pos passed to tpcf_build_grid)
+ * to d_out: count x nbins x (lmax+1) x (lmax+1) complex (re, im) float64,
+ * entry [p][b][l][m] for 0 <= m <= l (other entries zero). Requires step 2.
+ */
+tpcf_status tpcf_get_alm(tpcf_handle h, int64_t first, int64_t count, double* d_out);
+
+/*
+ * Step 3 -- contraction: NNN^m_{l1 l2}(b1, b2) summed over all primaries,
+ * real part (the imaginary part does not enter any even-parity multipole),
+ * degenerate triangles removed unless TPCF_F_KEEP_DEGENERATE.
+ * d_nnn_out: NULL, or (lmax+1)^3 x nbins x nbins float64 laid out
+ * [m][l1][l2][b1][b2] (entries with l1 < m or l2 < m are zero).
+ * Requires step 2.
+ */
+tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out);
+
+/*
+ * Step 4 -- multipoles zeta_{l1 l2 L}(b1, b2) for n_mult triples.
+ *  h_l1l2L: host array n_mult x 3 of (l1, l2, L) with l1, l2 <= lmax,
+ *           |l1 - l2| <= L <= l1 + l2 and l1 + l2 + L even (eq. (TripoSH)).
+ *  d_out  : n_mult x nbins x nbins float64.
+ * Requires step 3.
+ */
+tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2L,
+                            double* d_out);
+
+/*
+ * Steps 1-4 for ncat catalogues in one batched pass (the mock-catalogue use of
+ * Sec. 4.2 and 4.3). Catalogue c holds h_n[c] points stored after those of
+ * catalogues 0..c-1 in d_pos (sum h_n rows x 3 float64) and d_w (NULL = ones),
+ * and uses h_n_data[c] in its RRR. Results go to d_out, ncat x n_mult x nbins
+ * x nbins float64. Catalogues are processed in groups that fit the workspace
+ * limit; results do not depend on the grouping.
+ */
+tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n,
+                              const int64_t* h_n_data, const double* d_pos, const double* d_w,
+                              int32_t n_mult, const int32_t* h_l1l2L, double* d_out);
+
+/* Waits for all work enqueued by h. */
+tpcf_status tpcf_sync(tpcf_handle h);
+
+/* Ordered in-shell pairs counted by the last pair pass (valid after tpcf_sync). */
+tpcf_status tpcf_pair_count(tpcf_handle h, int64_t* h_out);
+
+/*
+ * Per-stage device time. With enable != 0 the handle records HIP events around
+ * each stage it enqueues; tpcf_stage_times then returns, after tpcf_sync, the
+ * summed milliseconds of the stages since the last reset and resets them:
+ *  h_ms[0] grid build, [1] pair binning, [2] pair harmonics (a_lm),
+ *  [3] contraction, [4] finalisation; h_launches[k] counts the launches timed.
+ * Either output may be NULL; at most n entries are written.
+ */
+tpcf_status tpcf_set_timing(tpcf_handle h, int enable);
+tpcf_status tpcf_stage_times(tpcf_handle h, int32_t n, double* h_ms, int64_t* h_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCF_H */

@@ -1,0 +1,1038 @@
+// Host runtime of libtpcf: the C ABI of include/tpcf.h.
+//
+// It validates arguments, plans the neighbour grid and the work split,
+// derives the constant tables of the estimator (spherical-harmonic scale
+// factors and the Legendre-product integrals that give both the tripolar
+// weights of eq. (slep2sugy) and the degenerate-triangle correction), owns the
+// device workspace and enqueues the kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tpcf.h"
+#include "tpcf_internal.h"
+
+namespace tpcf {
+size_t contract_lds_bytes(int mode, int nb, int lmax);
+}
+
+using namespace tpcf;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x74706366u;  // "tpcf"
+constexpr uint32_t kDead = 0xdeadbeefu;
+const double kPi = 3.14159265358979323846;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Timer {
+    hipEvent_t a, b;
+    int stage;
+};
+
+struct Chunk {
+    int64_t p_begin, p_end;  // sorted indices
+    int sub_begin, sub_end;  // global subchunk range
+};
+
+}  // namespace
+
+struct tpcf_handle_s {
+    uint32_t magic = kMagic;
+    tpcf_config cfg{};
+    std::vector<double> edges;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int nb = 0, lmax = 0, NV = 0, mode = 0, fp64 = 0;
+    int refine = 0;
+    int64_t limit = 0;
+    int64_t used = 0;
+    std::vector<DevBuf*> bufs;
+
+    // constants
+    std::vector<double> e2, vol, scale, sign_scale, gamma0;
+    std::vector<float> e2f, guard;
+    std::vector<unsigned char> lut;
+    std::vector<double> q;  // q[((l1*s1+l2)*s1+m)*(2lmax+1)+L]
+    std::vector<int64_t> goff;
+    int64_t gsize = 0;
+    DevBuf d_e2, d_e2f, d_guard, d_lut, d_runs, d_shift_f, d_goff, d_vol, d_scale, d_sign_scale,
+        d_gaunt;
+
+    // grid of the current group
+    Grid g{};
+    std::vector<StencilRun> runs;
+    int ncodes = 0;
+    int ncat = 0;
+    int64_t npts = 0;
+    std::vector<int64_t> pt_off;
+    std::vector<double> n_data;
+    bool unit_w = true;
+    DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pd, d_perm,
+        d_catid, d_flag;
+
+    // pair pass
+    std::vector<int64_t> sub_start;  // global subchunks (sorted index of first primary), + end
+    std::vector<int> cat_sub;        // [ncat+1]
+    std::vector<Chunk> chunks;
+    int64_t kc = 4096;
+    int64_t chunk_cap = 0;
+    unsigned long long list_cap = 0;
+    DevBuf d_list, d_lcursor, d_boff, d_cnt, d_A, d_subs, d_catsub, d_part, d_pself, d_G, d_S, d_nd,
+        d_mult, d_coefG, d_coefS, d_lflag;
+    int64_t ldA = 0;
+    int stage = 0;         // 0 nothing, 1 grid, 2 a_lm, 3 contracted
+    bool alm_kept = false; // A of the whole catalogue is resident (single chunk)
+    bool contracted_in_pass = false;
+    int64_t pairs = 0;
+    bool pairs_valid = false;
+
+    // timing
+    bool timing = false;
+    std::vector<Timer> timers;
+    double ms[5] = {0, 0, 0, 0, 0};
+    int64_t nl[5] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+tpcf_status fail(tpcf_handle h, tpcf_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+bool alive(tpcf_handle h) { return h && h->magic == kMagic; }
+
+tpcf_status hip_fail(tpcf_handle h, hipError_t e, const char* what) {
+    return fail(h, TPCF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                            \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return hip_fail(h, _e, #expr);    \
+    } while (0)
+
+// Grows a device buffer to at least `bytes` (contents are not preserved).
+tpcf_status ensure(tpcf_handle h, DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return TPCF_OK;
+    if (b.p) {
+        hipFree(b.p);
+        h->used -= (int64_t)b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) / 256 * 256;
+    if (h->used + (int64_t)bytes > h->limit)
+        return fail(h, TPCF_ERR_ALLOC, "workspace limit exceeded (" + std::to_string(h->used + bytes) +
+                                           " > " + std::to_string(h->limit) + " bytes)");
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(h, TPCF_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    h->used += (int64_t)bytes;
+    return TPCF_OK;
+}
+
+// Stream-ordered copy of a small host table; waits for it so that the host
+// memory may be released and the table is never overwritten under a kernel.
+tpcf_status upload(tpcf_handle h, DevBuf& b, const void* src, size_t bytes) {
+    tpcf_status st = ensure(h, b, bytes);
+    if (st != TPCF_OK) return st;
+    HIPCHK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return TPCF_OK;
+}
+
+void release(tpcf_handle h, DevBuf& b) {
+    if (b.p) {
+        hipFree(b.p);
+        h->used -= (int64_t)b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <class T> T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+// ---------------------------------------------------------------- timing
+
+void t_begin(tpcf_handle h, int stage, Timer& t) {
+    if (!h->timing) return;
+    t.stage = stage;
+    hipEventCreate(&t.a);
+    hipEventCreate(&t.b);
+    hipEventRecord(t.a, h->stream);
+}
+void t_end(tpcf_handle h, Timer& t) {
+    if (!h->timing) return;
+    hipEventRecord(t.b, h->stream);
+    h->timers.push_back(t);
+}
+
+// ---------------------------------------------------------------- constants
+
+// R_lm(z) for l = m..lmax at one z (R_mm = 1, R_{m+1,m} = z,
+// R_lm = z R_{l-1,m} - beta_lm R_{l-2,m}).
+void r_chain(int lmax, int m, double z, std::vector<double>& out) {
+    out.assign(lmax + 1, 0.0);
+    if (m > lmax) return;
+    out[m] = 1.0;
+    if (m + 1 <= lmax) out[m + 1] = z;
+    for (int l = m + 2; l <= lmax; ++l) {
+        const double beta = (double)((l + m - 1) * (l - m - 1)) / (double)((2 * l - 1) * (2 * l - 3));
+        out[l] = z * out[l - 1] - beta * out[l - 2];
+    }
+}
+
+double gamma_lm(int l, int m) {
+    double g = 1.0;
+    for (int k = 1; k <= 2 * m - 1; k += 2) g *= k;  // (2m-1)!!
+    for (int ll = m + 1; ll <= l; ++ll) g *= (double)(2 * ll - 1) / (double)(ll - m);
+    return g;
+}
+
+double norm_lm(int l, int m) {
+    double r = 1.0;
+    for (int k = l - m + 1; k <= l + m; ++k) r /= (double)k;
+    return std::sqrt((2.0 * l + 1.0) / (4.0 * kPi) * r);
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// q(l1,l2,m,L) = int_{-1}^{1} Nbar_l1m(z) Nbar_l2m(z) P_L(z) dz, where
+// Nbar_lm(z) = N_lm |P_l^m(z)| sign-free: the polar part shared by Y_l1m and
+// Y_l2m, so that conj(Y_l1m) Y_l2m = sum_L (2L+1)/2 q P_L(z) and the Gaunt
+// integral gives H (l1 l2 L; m -m 0) = (-1)^m 2 pi q / sqrt((2l1+1)(2l2+1)).
+void build_q(tpcf_handle h) {
+    const int lmax = h->lmax, s1 = lmax + 1, nL = 2 * lmax + 1;
+    std::vector<double> x, w;
+    gauss_legendre(64, x, w);
+    h->q.assign((size_t)s1 * s1 * s1 * nL, 0.0);
+    std::vector<std::vector<double>> Pm(s1), R;
+    std::vector<double> tmp, P0;
+    for (size_t i = 0; i < x.size(); ++i) {
+        const double z = x[i];
+        // Nbar_lm(z) for all l, m
+        std::vector<double> nb((size_t)s1 * s1, 0.0);
+        for (int m = 0; m <= lmax; ++m) {
+            r_chain(lmax, m, z, tmp);
+            const double sm = std::pow(std::max(0.0, 1.0 - z * z), 0.5 * m);
+            for (int l = m; l <= lmax; ++l) nb[l * s1 + m] = norm_lm(l, m) * gamma_lm(l, m) * tmp[l] * sm;
+        }
+        r_chain(2 * lmax, 0, z, P0);
+        for (int L = 0; L <= 2 * lmax; ++L) P0[L] *= gamma_lm(L, 0);  // Legendre P_L
+        for (int l1 = 0; l1 <= lmax; ++l1)
+            for (int l2 = 0; l2 <= lmax; ++l2)
+                for (int m = 0; m <= std::min(l1, l2); ++m) {
+                    const double f = w[i] * nb[l1 * s1 + m] * nb[l2 * s1 + m];
+                    double* qq = &h->q[(((size_t)l1 * s1 + l2) * s1 + m) * nL];
+                    for (int L = 0; L < nL; ++L) qq[L] += f * P0[L];
+                }
+    }
+    // exact zeros where parity or the triangle rule forbid the coupling
+    for (int l1 = 0; l1 <= lmax; ++l1)
+        for (int l2 = 0; l2 <= lmax; ++l2)
+            for (int m = 0; m <= std::min(l1, l2); ++m)
+                for (int L = 0; L < nL; ++L)
+                    if (((l1 + l2 + L) & 1) || L < std::abs(l1 - l2) || L > l1 + l2)
+                        h->q[(((size_t)l1 * s1 + l2) * s1 + m) * nL + L] = 0.0;
+}
+
+double qv(tpcf_handle h, int l1, int l2, int m, int L) {
+    const int s1 = h->lmax + 1, nL = 2 * h->lmax + 1;
+    return h->q[(((size_t)l1 * s1 + l2) * s1 + m) * nL + L];
+}
+
+double ulp32(double x) {
+    if (x <= 0) return std::ldexp(1.0, -149);
+    int e;
+    std::frexp(x, &e);  // x = f * 2^e, f in [0.5, 1)
+    return std::ldexp(1.0, e - 24);
+}
+
+tpcf_status setup_constants(tpcf_handle h) {
+    const int nb = h->nb, lmax = h->lmax, s1 = lmax + 1;
+    h->e2.resize(nb + 1);
+    h->e2f.resize(nb + 1);
+    for (int b = 0; b <= nb; ++b) {
+        h->e2[b] = h->edges[b] * h->edges[b];
+        h->e2f[b] = (float)h->e2[b];
+    }
+    h->vol.resize(nb);
+    for (int b = 0; b < nb; ++b)
+        h->vol[b] = 4.0 * kPi / 3.0 *
+                    (h->edges[b + 1] * h->edges[b + 1] * h->edges[b + 1] - h->edges[b] * h->edges[b] * h->edges[b]);
+    h->lut.resize(kLut);
+    const double span = h->e2[nb] - h->e2[0];
+    for (int i = 0; i < kLut; ++i) {
+        const double r2 = h->e2[0] + span * i / kLut;
+        int b = 0;
+        while (b + 1 < nb && r2 >= h->e2[b + 1]) ++b;
+        h->lut[i] = (unsigned char)b;
+    }
+    h->scale.assign((size_t)s1 * s1, 0.0);
+    h->sign_scale.assign((size_t)s1 * s1, 0.0);
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = 0; m <= l; ++m) {
+            h->scale[l * s1 + m] = norm_lm(l, m) * gamma_lm(l, m);
+            h->sign_scale[l * s1 + m] = ((m & 1) ? -1.0 : 1.0) * h->scale[l * s1 + m];
+        }
+    h->gamma0.resize(2 * lmax + 1);
+    for (int L = 0; L <= 2 * lmax; ++L) h->gamma0[L] = gamma_lm(L, 0);
+    build_q(h);
+    h->goff.resize(lmax + 2);
+    int64_t off = 0;
+    for (int m = 0; m <= lmax; ++m) {
+        h->goff[m] = off;
+        const int64_t K = (int64_t)nb * (lmax - m + 1);
+        off += K * K;
+    }
+    h->goff[lmax + 1] = off;
+    h->gsize = off;
+    // gaunt table for the NNN export: (2L+1)/2 q gamma0_L
+    const int nL = 2 * lmax + 1;
+    std::vector<double> gaunt((size_t)s1 * s1 * s1 * nL, 0.0);
+    for (int m = 0; m <= lmax; ++m)
+        for (int l1 = m; l1 <= lmax; ++l1)
+            for (int l2 = m; l2 <= lmax; ++l2)
+                for (int L = 0; L < nL; ++L)
+                    gaunt[(((size_t)m * s1 + l1) * s1 + l2) * nL + L] =
+                        0.5 * (2.0 * L + 1.0) * qv(h, l1, l2, m, L) * h->gamma0[L];
+    tpcf_status st;
+    if ((st = upload(h, h->d_e2, h->e2.data(), sizeof(double) * (nb + 1))) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_e2f, h->e2f.data(), sizeof(float) * (nb + 1))) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_lut, h->lut.data(), kLut)) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_goff, h->goff.data(), sizeof(int64_t) * (lmax + 2))) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_vol, h->vol.data(), sizeof(double) * nb)) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_scale, h->scale.data(), sizeof(double) * s1 * s1)) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_sign_scale, h->sign_scale.data(), sizeof(double) * s1 * s1)) != TPCF_OK)
+        return st;
+    if ((st = upload(h, h->d_gaunt, gaunt.data(), sizeof(double) * gaunt.size())) != TPCF_OK) return st;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return TPCF_OK;
+}
+
+// ---------------------------------------------------------------- grid plan
+
+// Stencil of cells that can hold a neighbour in [e0, rmax) of some point of
+// the home cell, as runs of consecutive oz for each (ox, oy).
+std::vector<StencilRun> make_stencil(int k, double hcell, double e0, double rmax) {
+    std::vector<StencilRun> runs;
+    for (int ox = -k; ox <= k; ++ox)
+        for (int oy = -k; oy <= k; ++oy) {
+            int cur_lo = 0;
+            bool open = false;
+            for (int oz = -k; oz <= k + 1; ++oz) {
+                bool keep = false;
+                if (oz <= k) {
+                    auto gap = [](int o) { return std::max(std::abs(o) - 1, 0); };
+                    auto far = [](int o) { return std::abs(o) + 1; };
+                    const double dmin = hcell * std::sqrt((double)(gap(ox) * gap(ox) + gap(oy) * gap(oy) + gap(oz) * gap(oz)));
+                    const double dmax = hcell * std::sqrt((double)(far(ox) * far(ox) + far(oy) * far(oy) + far(oz) * far(oz)));
+                    keep = dmin < rmax * (1.0 + 1e-9) && dmax > e0 * (1.0 - 1e-9);
+                }
+                if (keep && !open) { cur_lo = oz; open = true; }
+                if (!keep && open) {
+                    runs.push_back({ox, oy, cur_lo, oz - 1});
+                    open = false;
+                }
+            }
+        }
+    return runs;
+}
+
+int bits_for(int n) {
+    int b = 1;
+    while ((1 << b) < n) ++b;
+    return b;
+}
+
+tpcf_status plan_grid(tpcf_handle h, int64_t max_cat) {
+    const double L = h->cfg.box, rmax = h->edges[h->nb], e0 = h->edges[0];
+    int kmax = h->refine > 0 ? h->refine : 3;
+    for (int k = kmax; k >= 1; --k) {
+        const int nc = (int)std::floor(k * L / rmax);
+        if (nc < 2 * k + 1) continue;
+        if ((int64_t)nc * nc * nc * h->ncat > (1LL << 30)) continue;
+        const int K2 = 2 * k + 1;
+        const int cb = bits_for(K2 * K2 * K2);
+        if (max_cat >= (1LL << (32 - cb))) continue;
+        const double hc = L / nc;
+        std::vector<StencilRun> runs = make_stencil(k, hc, e0, rmax);
+        if (2 * (int)runs.size() > kMaxRuns) continue;
+        h->g.box = L;
+        h->g.nc = nc;
+        h->g.ncell = nc * nc * nc;
+        h->g.h = hc;
+        h->g.inv_h = nc / L;
+        h->g.hf = (float)hc;
+        h->g.boxf = (float)L;
+        h->g.k = k;
+        h->g.single = 0;
+        h->g.code_bits = cb;
+        h->g.idx_mask = (uint32_t)((1ULL << (32 - cb)) - 1);
+        h->runs = runs;
+        h->ncodes = K2 * K2 * K2;
+        break;
+    }
+    if (h->g.nc == 0) {
+        // one cell: every point is a candidate, minimum image per pair
+        if (max_cat >= (1LL << 31)) return fail(h, TPCF_ERR_RANGE, "catalogue too large");
+        h->g.box = L;
+        h->g.nc = 1;
+        h->g.ncell = 1;
+        h->g.h = L;
+        h->g.inv_h = 1.0 / L;
+        h->g.hf = (float)L;
+        h->g.boxf = (float)L;
+        h->g.k = 0;
+        h->g.single = 1;
+        h->g.code_bits = 1;
+        h->g.idx_mask = 0x7fffffffu;
+        h->runs = {{0, 0, 0, 0}};
+        h->ncodes = 1;
+    }
+    // shift table
+    const int k = h->g.k, K2 = 2 * k + 1;
+    std::vector<float> sh((size_t)h->ncodes * 3);
+    for (int c = 0; c < h->ncodes; ++c) {
+        const int ox = c / (K2 * K2) - k, oy = (c / K2) % K2 - k, oz = c % K2 - k;
+        sh[3 * c] = (float)(ox * h->g.h);
+        sh[3 * c + 1] = (float)(oy * h->g.h);
+        sh[3 * c + 2] = (float)(oz * h->g.h);
+    }
+    // guard bands of the FP32 binning: bound of the single-precision error of
+    // r^2 for pairs inside the stencil (see DESIGN notes in the kernel file)
+    const double span = h->g.single ? L : (k + 1) * h->g.h;
+    const double dd = 4.0 * ulp32(span);
+    h->guard.resize(h->nb + 1);
+    for (int b = 0; b <= h->nb; ++b) {
+        const double e = h->edges[b];
+        const double gb = 4.0 * (2.0 * std::sqrt(3.0) * std::max(e, dd) * dd + 4.0 * std::ldexp(e * e, -24) + 3.0 * dd * dd);
+        h->guard[b] = (float)gb;
+    }
+    tpcf_status st;
+    if ((st = upload(h, h->d_runs, h->runs.data(), sizeof(StencilRun) * h->runs.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_shift_f, sh.data(), sizeof(float) * sh.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_guard, h->guard.data(), sizeof(float) * (h->nb + 1))) != TPCF_OK) return st;
+    return TPCF_OK;
+}
+
+// ---------------------------------------------------------------- stages
+
+tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d_w,
+                             const std::vector<int64_t>& n, const std::vector<int64_t>& n_data) {
+    h->ncat = (int)n.size();
+    h->pt_off.assign(h->ncat + 1, 0);
+    int64_t max_cat = 0;
+    for (int c = 0; c < h->ncat; ++c) {
+        h->pt_off[c + 1] = h->pt_off[c] + n[c];
+        max_cat = std::max(max_cat, n[c]);
+    }
+    h->npts = h->pt_off[h->ncat];
+    h->n_data.assign(n_data.begin(), n_data.end());
+    h->unit_w = d_w == nullptr;
+    h->g = Grid{};
+    tpcf_status st = plan_grid(h, max_cat);
+    if (st != TPCF_OK) return st;
+    const int64_t N = h->npts;
+    const int64_t M = (int64_t)h->ncat * h->g.ncell;
+    if ((st = upload(h, h->d_pt_off, h->pt_off.data(), sizeof(int64_t) * (h->ncat + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_cellid, sizeof(int) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_count, sizeof(int) * (M + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_start, sizeof(int) * (M + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_cursor, sizeof(int) * (M + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_tmp, sizeof(int) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_orig, sizeof(int) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_pf, sizeof(float4) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_pw, sizeof(float) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_pd, sizeof(double4) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_perm, sizeof(int) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_catid, sizeof(int) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_flag, sizeof(int) * 4)) != TPCF_OK) return st;
+    Timer t;
+    t_begin(h, 0, t);
+    HIPCHK(launch_fill_i32(P<int>(h->d_count), M + 1, 0, h->stream));
+    HIPCHK(launch_fill_i32(P<int>(h->d_cursor), M + 1, 0, h->stream));
+    HIPCHK(launch_fill_i32(P<int>(h->d_flag), 4, 0, h->stream));
+    HIPCHK(launch_grid_assign(d_pos, d_w, N, P<int64_t>(h->d_pt_off), h->ncat, h->g, P<int>(h->d_cellid),
+                              P<int>(h->d_count), P<int>(h->d_flag), h->stream));
+    HIPCHK(launch_grid_scan(P<int>(h->d_count), M, P<int>(h->d_start), h->stream));
+    HIPCHK(launch_grid_scatter(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_cursor),
+                               P<int>(h->d_tmp), h->stream));
+    HIPCHK(launch_grid_order(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_tmp),
+                             P<int>(h->d_orig), h->stream));
+    HIPCHK(launch_grid_fill(d_pos, d_w, N, P<int>(h->d_orig), P<int>(h->d_cellid), h->g, P<float4>(h->d_pf),
+                            P<float>(h->d_pw), P<double4>(h->d_pd), P<int>(h->d_perm), P<int>(h->d_catid),
+                            h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
+// Splits every catalogue into subchunks of kc primaries and groups whole
+// subchunks into chunks whose a_lm operand fits the workspace share.
+tpcf_status plan_chunks(tpcf_handle h) {
+    const int64_t N = h->npts;
+    const size_t elem = h->fp64 ? 8 : 4;
+    const int64_t per_prim = (int64_t)h->nb * h->NV * (int64_t)elem;
+    // expected in-shell hits per primary (uniform density), for the list size
+    const double L3 = h->cfg.box * h->cfg.box * h->cfg.box;
+    const double rmax = h->edges[h->nb], e0 = h->edges[0];
+    const double shell = 4.0 * kPi / 3.0 * (rmax * rmax * rmax - e0 * e0 * e0);
+    int64_t maxn = 0;
+    for (int c = 0; c < h->ncat; ++c) maxn = std::max(maxn, h->pt_off[c + 1] - h->pt_off[c]);
+    const double hits = std::min((double)maxn, maxn / L3 * shell);
+    const double list_per = 4.0 * (2.0 * hits + 64.0);
+    int64_t budget = h->limit / 3;
+    int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
+    cap = std::min<int64_t>(cap, 1 << 20);
+    cap = std::max<int64_t>(h->kc, cap / h->kc * h->kc);
+    h->chunk_cap = cap;
+    h->sub_start.clear();
+    h->cat_sub.assign(h->ncat + 1, 0);
+    for (int c = 0; c < h->ncat; ++c) {
+        h->cat_sub[c] = (int)h->sub_start.size();
+        for (int64_t p = h->pt_off[c]; p < h->pt_off[c + 1]; p += h->kc) h->sub_start.push_back(p);
+    }
+    h->cat_sub[h->ncat] = (int)h->sub_start.size();
+    h->sub_start.push_back(N);
+    h->chunks.clear();
+    const int nsub = (int)h->sub_start.size() - 1;
+    int s = 0;
+    while (s < nsub) {
+        Chunk ch;
+        ch.sub_begin = s;
+        ch.p_begin = h->sub_start[s];
+        while (s < nsub && h->sub_start[s + 1] - ch.p_begin <= cap) ++s;
+        if (s == ch.sub_begin) ++s;
+        ch.sub_end = s;
+        ch.p_end = h->sub_start[s];
+        h->chunks.push_back(ch);
+    }
+    int64_t maxch = 0;
+    for (auto& ch : h->chunks) maxch = std::max(maxch, ch.p_end - ch.p_begin);
+    h->ldA = (maxch + 63) / 64 * 64;
+    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, (double)maxch * (2.0 * hits + 64.0)));
+    tpcf_status st;
+    if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_cnt, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_A, (size_t)h->nb * h->NV * h->ldA * elem)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_list, sizeof(uint32_t) * h->list_cap)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_lcursor, 64)) != TPCF_OK) return st;
+    // subchunk tables: per chunk, chunk-relative starts are uploaded on demand
+    if ((st = ensure(h, h->d_subs, sizeof(int) * (nsub + 1) + 64)) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_catsub, h->cat_sub.data(), sizeof(int) * (h->ncat + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_part, (size_t)nsub * h->gsize * sizeof(double))) != TPCF_OK) return st;
+    const int sw = h->nb * (2 * h->lmax + 2);
+    if ((st = ensure(h, h->d_pself, sizeof(double) * nsub * sw)) != TPCF_OK) return st;
+    return TPCF_OK;
+}
+
+tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
+    std::vector<int> rel(ch.sub_end - ch.sub_begin + 1);
+    for (int s = ch.sub_begin; s <= ch.sub_end; ++s) rel[s - ch.sub_begin] = (int)(h->sub_start[s] - ch.p_begin);
+    tpcf_status st;
+    // the table is chunk-specific; the copy is stream-ordered before its use
+    if ((st = upload(h, h->d_subs, rel.data(), sizeof(int) * rel.size())) != TPCF_OK) return st;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), 1, 0ull, h->stream));
+        HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 1, 0, h->stream));
+        BinArgs b{};
+        b.pf = P<float4>(h->d_pf);
+        b.pd = P<double4>(h->d_pd);
+        b.catid = P<int>(h->d_catid);
+        b.cell_start = P<int>(h->d_start);
+        b.pt_off = P<int64_t>(h->d_pt_off);
+        b.runs = P<StencilRun>(h->d_runs);
+        b.nruns = (int)h->runs.size();
+        b.g = h->g;
+        b.nb = h->nb;
+        b.e2 = P<double>(h->d_e2);
+        b.e2f = P<float>(h->d_e2f);
+        b.guard = P<float>(h->d_guard);
+        b.lut = P<unsigned char>(h->d_lut);
+        b.lut_scale = (float)(kLut / (h->e2[h->nb] - h->e2[0]));
+        b.p_begin = ch.p_begin;
+        b.p_end = ch.p_end;
+        b.list = P<uint32_t>(h->d_list);
+        b.cursor = P<unsigned long long>(h->d_lcursor);
+        b.capacity = h->list_cap;
+        b.boff = P<uint32_t>(h->d_boff);
+        b.cnt = P<uint32_t>(h->d_cnt);
+        b.overflow = P<int>(h->d_flag) + 1;
+        b.fp64 = h->fp64;
+        Timer t;
+        t_begin(h, 1, t);
+        HIPCHK(launch_pair_bin(b, h->stream));
+        t_end(h, t);
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, P<int>(h->d_flag) + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (!flag) break;
+        if (attempt == 5) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
+        unsigned long long ncap = std::min<unsigned long long>(4000000000ull, h->list_cap * 2);
+        if (ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
+        h->list_cap = ncap;
+        if ((st = ensure(h, h->d_list, sizeof(uint32_t) * h->list_cap)) != TPCF_OK) return st;
+    }
+    AlmArgs a{};
+    a.pf = P<float4>(h->d_pf);
+    a.pw = P<float>(h->d_pw);
+    a.pd = P<double4>(h->d_pd);
+    a.catid = P<int>(h->d_catid);
+    a.pt_off = P<int64_t>(h->d_pt_off);
+    a.g = h->g;
+    a.nb = h->nb;
+    a.lmax = h->lmax;
+    a.p_begin = ch.p_begin;
+    a.p_end = ch.p_end;
+    a.list = P<uint32_t>(h->d_list);
+    a.boff = P<uint32_t>(h->d_boff);
+    a.cnt = P<uint32_t>(h->d_cnt);
+    a.A = h->d_A.p;
+    a.ldA = h->ldA;
+    a.shift_f = P<float>(h->d_shift_f);
+    a.ncodes = h->ncodes;
+    Timer t;
+    t_begin(h, 2, t);
+    HIPCHK(launch_pair_alm(a, h->fp64, h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
+tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
+    const int nsub = ch.sub_end - ch.sub_begin;
+    Timer t;
+    t_begin(h, 3, t);
+    ContractArgs c{};
+    c.A = h->d_A.p;
+    c.ldA = h->ldA;
+    c.pd = P<double4>(h->d_pd);
+    c.p_begin = ch.p_begin;
+    c.nb = h->nb;
+    c.lmax = h->lmax;
+    c.sub_start = P<int>(h->d_subs);
+    c.nsub = nsub;
+    c.sub_base = ch.sub_begin;
+    c.part32 = nullptr;
+    c.part64 = P<double>(h->d_part);
+    c.gsize = h->gsize;
+    c.goff = P<int64_t>(h->d_goff);
+    c.mode = h->mode;
+    c.unit_weights = h->unit_w ? 1 : 0;
+    HIPCHK(launch_contract(c, h->stream));
+    SelfArgs s{};
+    s.A = h->d_A.p;
+    s.ldA = h->ldA;
+    s.pd = P<double4>(h->d_pd);
+    s.cnt = P<uint32_t>(h->d_cnt);
+    s.p_begin = ch.p_begin;
+    s.nb = h->nb;
+    s.lmax = h->lmax;
+    s.sub_start = P<int>(h->d_subs);
+    s.nsub = nsub;
+    s.sub_base = ch.sub_begin;
+    s.part = P<double>(h->d_pself);
+    s.fp64 = h->fp64;
+    HIPCHK(launch_self_moments(s, h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
+tpcf_status reduce_group(tpcf_handle h) {
+    tpcf_status st;
+    const int sw = h->nb * (2 * h->lmax + 2);
+    if ((st = ensure(h, h->d_G, sizeof(double) * h->ncat * h->gsize)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_S, sizeof(double) * h->ncat * sw)) != TPCF_OK) return st;
+    Timer t;
+    t_begin(h, 3, t);
+    HIPCHK(launch_reduce_partials(nullptr, P<double>(h->d_part), h->gsize,
+                                  P<int>(h->d_catsub), h->ncat, P<double>(h->d_G), h->stream));
+    HIPCHK(launch_reduce_partials(nullptr, P<double>(h->d_pself), sw, P<int>(h->d_catsub), h->ncat,
+                                  P<double>(h->d_S), h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
+tpcf_status check_mults(tpcf_handle h, int32_t n_mult, const int32_t* m) {
+    if (n_mult < 1 || !m) return fail(h, TPCF_ERR_ARG, "n_mult must be >= 1 with a host triple array");
+    for (int t = 0; t < n_mult; ++t) {
+        const int l1 = m[3 * t], l2 = m[3 * t + 1], L = m[3 * t + 2];
+        if (l1 < 0 || l2 < 0 || L < 0 || l1 > h->lmax || l2 > h->lmax || L < std::abs(l1 - l2) ||
+            L > l1 + l2 || ((l1 + l2 + L) & 1))
+            return fail(h, TPCF_ERR_ARG, "invalid multipole triple (" + std::to_string(l1) + "," +
+                                             std::to_string(l2) + "," + std::to_string(L) + ")");
+    }
+    return TPCF_OK;
+}
+
+tpcf_status finalize_group(tpcf_handle h, int32_t n_mult, const int32_t* mult, double* d_out) {
+    const int lmax = h->lmax, s1 = lmax + 1, nL = 2 * lmax + 1;
+    std::vector<double> cg((size_t)n_mult * s1, 0.0), cs((size_t)n_mult * s1 * nL, 0.0);
+    const bool lit = (h->cfg.flags & TPCF_F_PAPER_LITERAL) != 0;
+    for (int t = 0; t < n_mult; ++t) {
+        const int l1 = mult[3 * t], l2 = mult[3 * t + 1], L = mult[3 * t + 2];
+        const double f = lit ? 4.0 * kPi / std::sqrt((2.0 * l1 + 1.0) * (2.0 * l2 + 1.0)) : 1.0;
+        for (int m = 0; m <= std::min(l1, l2); ++m) {
+            const double base = 8.0 * kPi * kPi * (2.0 * L + 1.0) * qv(h, l1, l2, m, L) * (m > 0 ? 2.0 : 1.0) * f;
+            cg[t * s1 + m] = base * h->scale[l1 * s1 + m] * h->scale[l2 * s1 + m];
+            for (int L2 = 0; L2 < nL; ++L2)
+                cs[((size_t)t * s1 + m) * nL + L2] = base * 0.5 * (2.0 * L2 + 1.0) * qv(h, l1, l2, m, L2) * h->gamma0[L2];
+        }
+    }
+    tpcf_status st;
+    if ((st = upload(h, h->d_mult, mult, sizeof(int) * 3 * n_mult)) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_coefG, cg.data(), sizeof(double) * cg.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_coefS, cs.data(), sizeof(double) * cs.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_nd, h->n_data.data(), sizeof(double) * h->ncat)) != TPCF_OK) return st;
+    FinalArgs a{};
+    a.G = P<double>(h->d_G);
+    a.gsize = h->gsize;
+    a.goff = P<int64_t>(h->d_goff);
+    a.S = P<double>(h->d_S);
+    a.nd = P<double>(h->d_nd);
+    a.nb = h->nb;
+    a.lmax = lmax;
+    a.n_mult = n_mult;
+    a.mult = P<int>(h->d_mult);
+    a.coefG = P<double>(h->d_coefG);
+    a.coefS = P<double>(h->d_coefS);
+    a.vol = P<double>(h->d_vol);
+    const double L = h->cfg.box;
+    a.inv_box6 = 1.0 / (L * L * L * L * L * L);
+    a.subtract_self = (h->cfg.flags & TPCF_F_KEEP_DEGENERATE) ? 0 : 1;
+    a.out = d_out;
+    a.ncat = h->ncat;
+    Timer t;
+    t_begin(h, 4, t);
+    HIPCHK(launch_finalize(a, h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
+tpcf_status check_nonfinite(tpcf_handle h) {
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, P<int>(h->d_flag), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (flag) return fail(h, TPCF_ERR_DEVICE, std::to_string(flag) + " non-finite input position(s)");
+    return TPCF_OK;
+}
+
+// pair pass over every chunk; contracts each chunk right away when the
+// operand cannot be kept for the whole group
+tpcf_status pair_pass(tpcf_handle h, bool contract_now) {
+    tpcf_status st;
+    for (const Chunk& ch : h->chunks) {
+        if ((st = pair_chunk(h, ch)) != TPCF_OK) return st;
+        if (contract_now && (st = contract_chunk(h, ch)) != TPCF_OK) return st;
+    }
+    return TPCF_OK;
+}
+
+tpcf_status validate_config(const tpcf_config* c) {
+    if (!c) return TPCF_ERR_ARG;
+    if (!(c->box > 0.0) || !std::isfinite(c->box)) return TPCF_ERR_ARG;
+    if (c->nbins < 1 || c->nbins > kMaxBins || !c->h_edges) return c->h_edges ? TPCF_ERR_RANGE : TPCF_ERR_ARG;
+    for (int b = 0; b <= c->nbins; ++b)
+        if (!std::isfinite(c->h_edges[b])) return TPCF_ERR_RANGE;
+    for (int b = 0; b < c->nbins; ++b)
+        if (!(c->h_edges[b + 1] > c->h_edges[b])) return TPCF_ERR_RANGE;
+    if (c->h_edges[0] < 0.0 || c->h_edges[c->nbins] > 0.5 * c->box) return TPCF_ERR_RANGE;
+    if (c->lmax < 0 || c->lmax > kMaxLmax) return TPCF_ERR_RANGE;
+    if (c->precision < 0 || c->precision > 3) return TPCF_ERR_ARG;
+    if (c->grid_refine < 0 || c->grid_refine > 4) return TPCF_ERR_RANGE;
+    if (c->workspace_limit < 0) return TPCF_ERR_ARG;
+    if (c->flags & ~(uint32_t)(TPCF_F_KEEP_DEGENERATE | TPCF_F_PAPER_LITERAL)) return TPCF_ERR_ARG;
+    const int mode = c->precision;
+    if (contract_lds_bytes(mode, c->nbins, c->lmax) > 160 * 1024) return TPCF_ERR_RANGE;
+    return TPCF_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+tpcf_status tpcf_create(const tpcf_config* cfg, int device, void* hip_stream, tpcf_handle* out) {
+    if (!out) return TPCF_ERR_ARG;
+    *out = nullptr;
+    tpcf_status st = validate_config(cfg);
+    if (st != TPCF_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TPCF_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return TPCF_ERR_DEVICE;
+    tpcf_handle h = new tpcf_handle_s();
+    h->cfg = *cfg;
+    h->edges.assign(cfg->h_edges, cfg->h_edges + cfg->nbins + 1);
+    h->cfg.h_edges = h->edges.data();
+    h->device = device;
+    h->stream = (hipStream_t)hip_stream;
+    h->nb = cfg->nbins;
+    h->lmax = cfg->lmax;
+    h->NV = n_values(cfg->lmax);
+    h->mode = cfg->precision;  // contraction mode: 0 fp64, 1 fp32, 2 bf16x3, 3 bf16x6
+    h->fp64 = cfg->precision == TPCF_PREC_FP64 ? 1 : 0;
+    h->refine = cfg->grid_refine;
+    h->limit = cfg->workspace_limit > 0 ? cfg->workspace_limit : (64LL << 30);
+    st = setup_constants(h);
+    if (st != TPCF_OK) {
+        tpcf_destroy(h);
+        return st;
+    }
+    *out = h;
+    return TPCF_OK;
+}
+
+void tpcf_destroy(tpcf_handle h) {
+    if (!alive(h)) return;
+    hipSetDevice(h->device);
+    hipStreamSynchronize(h->stream);
+    for (Timer& t : h->timers) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_lut, &h->d_runs, &h->d_shift_f, &h->d_goff,
+                     &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
+                     &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
+                     &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_lcursor, &h->d_boff,
+                     &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
+                     &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag};
+    for (DevBuf* b : all) release(h, *b);
+    h->magic = kDead;
+    delete h;
+}
+
+const char* tpcf_last_error(tpcf_handle h) {
+    if (!alive(h)) return "invalid or destroyed tpcf handle";
+    return h->err.c_str();
+}
+
+tpcf_status tpcf_build_grid(tpcf_handle h, const double* d_pos, const double* d_w, int64_t n,
+                            int64_t n_data) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_pos) return fail(h, TPCF_ERR_ARG, "d_pos is NULL");
+    if (n < 1 || n > (1LL << 27)) return fail(h, TPCF_ERR_ARG, "n must be in 1 .. 2^27");
+    if (n_data < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
+    HIPCHK(hipSetDevice(h->device));
+    h->stage = 0;
+    h->pairs_valid = false;
+    tpcf_status st = build_grid_group(h, d_pos, d_w, {n}, {n_data});
+    if (st != TPCF_OK) return st;
+    h->stage = 1;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_alm_accumulate(tpcf_handle h) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (h->stage < 1) return fail(h, TPCF_ERR_STATE, "tpcf_build_grid must come first");
+    HIPCHK(hipSetDevice(h->device));
+    tpcf_status st = check_nonfinite(h);
+    if (st != TPCF_OK) return st;
+    if ((st = plan_chunks(h)) != TPCF_OK) return st;
+    const bool single = h->chunks.size() == 1;
+    if ((st = pair_pass(h, !single)) != TPCF_OK) return st;
+    h->alm_kept = single;
+    h->contracted_in_pass = !single;
+    h->pairs_valid = false;
+    h->stage = 2;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_get_alm(tpcf_handle h, int64_t first, int64_t count, double* d_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (h->stage < 2) return fail(h, TPCF_ERR_STATE, "tpcf_alm_accumulate must come first");
+    if (!h->alm_kept) return fail(h, TPCF_ERR_STATE, "a_lm of this catalogue is not resident (several chunks)");
+    if (!d_out || first < 0 || count < 0 || first + count > h->npts)
+        return fail(h, TPCF_ERR_ARG, "bad primary range or NULL output");
+    HIPCHK(hipSetDevice(h->device));
+    AlmExportArgs a{};
+    a.A = h->d_A.p;
+    a.ldA = h->ldA;
+    a.perm = P<int>(h->d_perm);
+    a.p_begin = h->chunks[0].p_begin;
+    a.first = first;
+    a.count = count;
+    a.nb = h->nb;
+    a.lmax = h->lmax;
+    a.sign_scale = P<double>(h->d_sign_scale);
+    a.fp64 = h->fp64;
+    a.out = d_out;
+    HIPCHK(launch_export_alm(a, h->stream));
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (h->stage < 2) return fail(h, TPCF_ERR_STATE, "tpcf_alm_accumulate must come first");
+    HIPCHK(hipSetDevice(h->device));
+    tpcf_status st;
+    if (h->stage == 2) {
+        if (!h->contracted_in_pass)
+            for (const Chunk& ch : h->chunks)
+                if ((st = contract_chunk(h, ch)) != TPCF_OK) return st;
+        if ((st = reduce_group(h)) != TPCF_OK) return st;
+        h->stage = 3;
+    }
+    if (d_nnn_out) {
+        NnnArgs a{};
+        a.G = P<double>(h->d_G);
+        a.goff = P<int64_t>(h->d_goff);
+        a.S = P<double>(h->d_S);
+        a.nb = h->nb;
+        a.lmax = h->lmax;
+        a.scale = P<double>(h->d_scale);
+        a.gaunt = P<double>(h->d_gaunt);
+        a.subtract_self = (h->cfg.flags & TPCF_F_KEEP_DEGENERATE) ? 0 : 1;
+        a.out = d_nnn_out;
+        HIPCHK(launch_export_nnn(a, h->stream));
+    }
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2L, double* d_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    tpcf_status st = check_mults(h, n_mult, h_l1l2L);
+    if (st != TPCF_OK) return st;
+    if (!d_out) return fail(h, TPCF_ERR_ARG, "d_out is NULL");
+    if (h->stage < 3) return fail(h, TPCF_ERR_STATE, "tpcf_contract must come first");
+    HIPCHK(hipSetDevice(h->device));
+    return finalize_group(h, n_mult, h_l1l2L, d_out);
+}
+
+tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n, const int64_t* h_n_data,
+                              const double* d_pos, const double* d_w, int32_t n_mult,
+                              const int32_t* h_l1l2L, double* d_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (ncat < 1 || !h_n || !h_n_data || !d_pos || !d_out)
+        return fail(h, TPCF_ERR_ARG, "ncat >= 1 and non-NULL h_n, h_n_data, d_pos, d_out required");
+    tpcf_status st = check_mults(h, n_mult, h_l1l2L);
+    if (st != TPCF_OK) return st;
+    for (int c = 0; c < ncat; ++c) {
+        if (h_n[c] < 1 || h_n[c] > (1LL << 27)) return fail(h, TPCF_ERR_ARG, "catalogue size out of range");
+        if (h_n_data[c] < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
+    }
+    HIPCHK(hipSetDevice(h->device));
+    // groups of whole catalogues whose points fit a quarter of the workspace
+    const int64_t per_point = 96;
+    const int64_t max_pts = std::max<int64_t>(1, std::min<int64_t>((h->limit / 4) / per_point, (1LL << 31) - 1));
+    int c0 = 0;
+    int64_t pos_off = 0;
+    const int64_t per_out = (int64_t)n_mult * h->nb * h->nb;
+    while (c0 < ncat) {
+        int c1 = c0;
+        int64_t pts = 0;
+        while (c1 < ncat && (c1 == c0 || pts + h_n[c1] <= max_pts)) pts += h_n[c1++];
+        std::vector<int64_t> n(h_n + c0, h_n + c1), nd(h_n_data + c0, h_n_data + c1);
+        h->stage = 0;
+        if ((st = build_grid_group(h, d_pos + 3 * pos_off, d_w ? d_w + pos_off : nullptr, n, nd)) != TPCF_OK)
+            return st;
+        if ((st = check_nonfinite(h)) != TPCF_OK) return st;
+        if ((st = plan_chunks(h)) != TPCF_OK) return st;
+        if ((st = pair_pass(h, true)) != TPCF_OK) return st;
+        if ((st = reduce_group(h)) != TPCF_OK) return st;
+        h->stage = 3;
+        if ((st = finalize_group(h, n_mult, h_l1l2L, d_out + per_out * c0)) != TPCF_OK) return st;
+        pos_off += pts;
+        c0 = c1;
+    }
+    h->alm_kept = false;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_sync(tpcf_handle h) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_pair_count(tpcf_handle h, int64_t* h_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!h_out) return fail(h, TPCF_ERR_ARG, "h_out is NULL");
+    if (h->stage < 3) return fail(h, TPCF_ERR_STATE, "pair counts are available after tpcf_contract");
+    HIPCHK(hipSetDevice(h->device));
+    const int sw = h->nb * (2 * h->lmax + 2);
+    std::vector<double> S((size_t)h->ncat * sw);
+    HIPCHK(hipMemcpyAsync(S.data(), h->d_S.p, sizeof(double) * S.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    for (int c = 0; c < h->ncat; ++c)
+        for (int b = 0; b < h->nb; ++b) tot += S[(size_t)c * sw + b * (2 * h->lmax + 2) + 2 * h->lmax + 1];
+    *h_out = (int64_t)std::llround(tot);
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_set_timing(tpcf_handle h, int enable) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    h->timing = enable != 0;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_stage_times(tpcf_handle h, int32_t n, double* h_ms, int64_t* h_launches) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (Timer& t : h->timers) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t.a, t.b);
+        h->ms[t.stage] += ms;
+        h->nl[t.stage] += 1;
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    h->timers.clear();
+    for (int i = 0; i < 5 && i < n; ++i) {
+        if (h_ms) h_ms[i] = h->ms[i];
+        if (h_launches) h_launches[i] = h->nl[i];
+    }
+    for (int i = 0; i < 5; ++i) {
+        h->ms[i] = 0.0;
+        h->nl[i] = 0;
+    }
+    return TPCF_OK;
+}
+
+}  // extern "C"

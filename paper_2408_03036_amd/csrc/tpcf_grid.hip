@@ -1,0 +1,203 @@
+// Neighbour grid: a counting sort of the points by cell (the linked-list
+// spatial partition of Sec. 4.1, laid out as contiguous per-cell ranges so
+// the pair pass reads neighbour cells with coalesced loads).
+//
+// Steps: assign (wrap, cell id, histogram) -> scan (cell starts) ->
+// scatter (atomic slots) -> order (stable rank by input index inside a cell,
+// so the layout is deterministic) -> fill (sorted SoA copies).
+#include "tpcf_internal.h"
+
+namespace tpcf {
+
+namespace {
+
+__device__ inline double wrap_coord(double x, double L) {
+    double y = fmod(x, L);
+    if (y < 0.0) y += L;
+    if (y >= L) y -= L;
+    return y;
+}
+
+__device__ inline int cell_of(double x, const Grid& g) {
+    int c = (int)(x * g.inv_h);
+    c = c < 0 ? 0 : c;
+    return c >= g.nc ? g.nc - 1 : c;
+}
+
+__device__ inline int find_cat(const int64_t* off, int ncat, int64_t i) {
+    int lo = 0, hi = ncat;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_grid_assign(const double* __restrict__ pos, int64_t n,
+                              const int64_t* __restrict__ pt_off, int ncat, Grid g,
+                              int* __restrict__ cellid, int* __restrict__ count,
+                              int* __restrict__ nonfinite) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        atomicAdd(nonfinite, 1);
+        x = y = z = 0.0;
+    }
+    x = wrap_coord(x, g.box);
+    y = wrap_coord(y, g.box);
+    z = wrap_coord(z, g.box);
+    int c = find_cat(pt_off, ncat, i);
+    int id = c * g.ncell + (cell_of(x, g) * g.nc + cell_of(y, g)) * g.nc + cell_of(z, g);
+    cellid[i] = id;
+    atomicAdd(&count[id], 1);
+}
+
+// Single-workgroup exclusive scan: each thread scans a contiguous segment.
+__global__ void __launch_bounds__(1024) k_grid_scan(const int* __restrict__ count, int64_t m,
+                                                    int* __restrict__ start) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int64_t seg = (m + 1023) / 1024;
+    const int64_t a = t * seg;
+    const int64_t b = a + seg < m ? a + seg : m;
+    int s = 0;
+    for (int64_t i = a; i < b; ++i) s += count[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int64_t i = a; i < b; ++i) {
+        start[i] = run;
+        run += count[i];
+    }
+    if (t == 1023) start[m] = part[1023];
+}
+
+__global__ void k_grid_scatter(const int* __restrict__ cellid, int64_t n,
+                               const int* __restrict__ start, int* __restrict__ cursor,
+                               int* __restrict__ tmp_idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cellid[i];
+    int slot = atomicAdd(&cursor[c], 1);
+    tmp_idx[start[c] + slot] = (int)i;
+}
+
+// Stable placement: a point's rank in its cell is the number of points of the
+// same cell with a smaller input index.
+__global__ void k_grid_order(const int* __restrict__ cellid, int64_t n,
+                             const int* __restrict__ start, const int* __restrict__ tmp_idx,
+                             int* __restrict__ orig) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cellid[i];
+    int a = start[c], b = start[c + 1];
+    int rank = 0;
+    for (int s = a; s < b; ++s) rank += tmp_idx[s] < (int)i;
+    orig[a + rank] = (int)i;
+}
+
+__global__ void k_grid_fill(const double* __restrict__ pos, const double* __restrict__ w,
+                            int64_t n, const int* __restrict__ orig,
+                            const int* __restrict__ cellid, Grid g, float4* __restrict__ pf,
+                            float* __restrict__ pw, double4* __restrict__ pd,
+                            int* __restrict__ perm, int* __restrict__ catid) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = orig[s];
+    double x = pos[3 * (int64_t)i], y = pos[3 * (int64_t)i + 1], z = pos[3 * (int64_t)i + 2];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) x = y = z = 0.0;
+    x = wrap_coord(x, g.box);
+    y = wrap_coord(y, g.box);
+    z = wrap_coord(z, g.box);
+    double wi = w ? w[i] : 1.0;
+    int id = cellid[i];
+    int cat = id / g.ncell;
+    int loc = id - cat * g.ncell;
+    int cz = loc % g.nc;
+    int cy = (loc / g.nc) % g.nc;
+    int cx = loc / (g.nc * g.nc);
+    // Offsets from the cell's lower corner; exact in FP64, rounded once to FP32.
+    float4 q;
+    q.x = (float)(x - cx * g.h);
+    q.y = (float)(y - cy * g.h);
+    q.z = (float)(z - cz * g.h);
+    q.w = (float)cz;
+    pf[s] = q;
+    pw[s] = (float)wi;
+    pd[s] = make_double4(x, y, z, wi);
+    perm[i] = (int)s;
+    catid[s] = cat;
+}
+
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_grid_assign(const double* pos, const double*, int64_t n, const int64_t* pt_off,
+                              int ncat, Grid g, int* cellid, int* count, int* nonfinite,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid_assign, dim3(nblk(n, 256)), dim3(256), 0, s, pos, n, pt_off, ncat, g,
+                       cellid, count, nonfinite);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_scan(const int* count, int64_t m, int* start, hipStream_t s) {
+    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, count, m, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, int* cursor,
+                               int* tmp_idx, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid_scatter, dim3(nblk(n, 256)), dim3(256), 0, s, cellid, n, start,
+                       cursor, tmp_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, const int* tmp_idx,
+                             int* orig, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid_order, dim3(nblk(n, 256)), dim3(256), 0, s, cellid, n, start,
+                       tmp_idx, orig);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const int* orig,
+                            const int* cellid, Grid g, float4* pf, float* pw, double4* pd,
+                            int* perm, int* catid, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid_fill, dim3(nblk(n, 256)), dim3(256), 0, s, pos, w, n, orig, cellid,
+                       g, pf, pw, pd, perm, catid);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace tpcf

@@ -1,0 +1,197 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libtpcf. Not part of the public ABI (include/tpcf.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpcf {
+
+constexpr int kMaxBins = 32;
+constexpr int kMaxLmax = 12;
+constexpr int kMaxRuns = 2 * 81;   // stencil column runs after z-wrap splitting (grid_refine <= 4)
+constexpr int kMaxCodes = 729;     // (2k+1)^3 stencil offsets for grid_refine <= 4
+constexpr int kWave = 64;
+
+// Number of real accumulator values per (primary, bin): a_lm for m = 0 (real,
+// l = 0..lmax), m >= 1 (re and im, l = m..lmax), then the 2 lmax + 1 moments
+// of the squared weights sum_j w_j^2 R^0_L(z) for L = 0..2 lmax.
+__host__ __device__ constexpr int n_alm_values(int lmax) { return (lmax + 1) * (lmax + 1); }
+__host__ __device__ constexpr int n_values(int lmax) { return (lmax + 1) * (lmax + 1) + 2 * lmax + 1; }
+// Offset of the first value of order m inside a bin's value vector.
+// m = 0 occupies [0, lmax]; m >= 1 occupies 2 (lmax - m + 1) values: re for
+// l = m..lmax, then im for l = m..lmax.
+__host__ __device__ constexpr int value_offset(int lmax, int m) {
+    return m == 0 ? 0 : (lmax + 1) + (m - 1) * (2 * lmax + 2 - m);
+}
+
+// Neighbour grid of one build (all catalogues of a group share it).
+struct Grid {
+    double box;        // L
+    double h;          // cell side L / nc
+    double inv_h;      // nc / L
+    float hf;          // (float)h
+    float boxf;        // (float)L
+    int nc;            // cells per side
+    int ncell;         // nc^3
+    int k;             // stencil half-width in cells (0 in single-cell mode)
+    int single;        // 1: one cell, minimum image per pair
+    int code_bits;     // bits of the stencil-offset code in a list entry
+    uint32_t idx_mask; // mask of the catalogue-relative point index in a list entry
+};
+
+struct StencilRun { int ox, oy, oz_lo, oz_hi; };
+
+// Per-catalogue bookkeeping of a group (device arrays).
+struct CatArrays {
+    const int64_t* pt_off;   // [ncat+1] first point of each catalogue (input = sorted order ranges)
+    int ncat;
+};
+
+// ---------------------------------------------------------------- launchers
+// Grid build (tpcf_grid.hip)
+hipError_t launch_grid_assign(const double* pos, const double* w, int64_t n, const int64_t* pt_off,
+                              int ncat, Grid g, int* cellid, int* count, int* nonfinite,
+                              hipStream_t s);
+hipError_t launch_grid_scan(const int* count, int64_t m, int* start, hipStream_t s);
+hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, int* cursor,
+                               int* tmp_idx, hipStream_t s);
+hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, const int* tmp_idx,
+                             int* orig, hipStream_t s);
+hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const int* orig,
+                            const int* cellid, Grid g, float4* pf, float* pw, double4* pd,
+                            int* perm, int* catid, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+
+// Pair pass (tpcf_pairs.hip)
+struct BinArgs {
+    const float4* pf;        // sorted (xr, yr, zr, iz) cell-relative FP32
+    const double4* pd;       // sorted (x, y, z, w) FP64 wrapped
+    const int* catid;        // sorted catalogue id
+    const int* cell_start;   // [ncat*ncell+1]
+    const int64_t* pt_off;   // [ncat+1]
+    const StencilRun* runs;  // stencil runs
+    int nruns;
+    Grid g;
+    int nb;
+    const double* e2;        // [nb+1] squared edges (FP64)
+    const float* e2f;        // [nb+1] squared edges (FP32)
+    const float* guard;      // [nb+1] FP32 guard band around each squared edge
+    const unsigned char* lut;// [kLut] bin lookup over squared separation
+    float lut_scale;         // kLut / (e2[nb] - e2[0])
+    int64_t p_begin, p_end;  // primaries (sorted indices) of this chunk
+    uint32_t* list;          // hit lists of the chunk
+    unsigned long long* cursor; // [1] bump allocator in `list`
+    unsigned long long capacity;
+    uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists
+    uint32_t* cnt;           // [(p_end-p_begin)*nb] lengths
+    int* overflow;           // [1] set when `list` is too small
+    int fp64;                // exact FP64 binning for every pair (plain FP64 path)
+};
+constexpr int kLut = 1024;
+hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);
+
+struct AlmArgs {
+    const float4* pf;
+    const float* pw;
+    const double4* pd;
+    const int* catid;
+    const int64_t* pt_off;
+    Grid g;
+    int nb;
+    int lmax;
+    int64_t p_begin, p_end;
+    const uint32_t* list;
+    const uint32_t* boff;
+    const uint32_t* cnt;
+    void* A;                 // [nb][nvalues][ldA] float or double
+    int64_t ldA;             // leading dimension (primaries of the chunk, padded)
+    const float* shift_f;    // [ncodes*3] stencil offset in length units (FP32)
+    const int* shift_i;      // [ncodes*3] stencil offset in cells
+    int ncodes;
+};
+hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s);
+
+// Contraction (tpcf_contract.hip)
+struct ContractArgs {
+    const void* A;           // [nb][nvalues][ldA]
+    int64_t ldA;
+    const double4* pd;       // weights of the primaries (w in .w), sorted order
+    int64_t p_begin;         // first primary of the chunk (sorted index)
+    int nb, lmax;
+    const int* sub_start;    // [nsub+1] chunk-relative first primary of each subchunk
+    int nsub;
+    int sub_base;            // global index of the first subchunk of this chunk
+    float* part32;           // partial sums (FP32 modes): [nsub_total][gsize]
+    double* part64;          // partial sums (FP64 mode)
+    int64_t gsize;           // sum_m K_m^2
+    const int64_t* goff;     // [lmax+1] offset of G_m inside a partial
+    int mode;                // 0 fp64, 1 fp32, 2 bf16x3
+    int unit_weights;        // all weights 1: skip the weight multiply
+};
+hipError_t launch_contract(const ContractArgs& a, hipStream_t s);
+
+struct SelfArgs {
+    const void* A;
+    int64_t ldA;
+    const double4* pd;
+    const uint32_t* cnt;
+    int64_t p_begin;
+    int nb, lmax;
+    const int* sub_start;
+    int nsub;
+    int sub_base;
+    double* part;            // [nsub_total][nb*(2lmax+2)]: moments then pair count per bin
+    int fp64;
+};
+hipError_t launch_self_moments(const SelfArgs& a, hipStream_t s);
+
+// Fixed-order sums of subchunk partials per catalogue.
+hipError_t launch_reduce_partials(const float* p32, const double* p64, int64_t width,
+                                  const int* cat_sub, int ncat, double* out, hipStream_t s);
+
+struct FinalArgs {
+    const double* G;         // [ncat][gsize] (FP64, upper-triangle-complete symmetric)
+    int64_t gsize;
+    const int64_t* goff;     // [lmax+1]
+    const double* S;         // [ncat][nb*(2lmax+2)] self moments and pair counts
+    const double* nd;        // [ncat] N_D
+    int nb, lmax;
+    int n_mult;
+    const int* mult;         // [n_mult*3]
+    const double* coefG;     // [n_mult][lmax+1] coefficient of s s G_m
+    const double* coefS;     // [n_mult][lmax+1][2lmax+1] coefficient of the self moments
+    const double* vol;       // [nb] shell volumes
+    double inv_box6;
+    int subtract_self;
+    double* out;             // [ncat][n_mult][nb][nb]
+    int ncat;
+};
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
+
+struct NnnArgs {
+    const double* G;         // [gsize] one catalogue
+    const int64_t* goff;
+    const double* S;         // [nb*(2lmax+2)]
+    int nb, lmax;
+    const double* scale;     // [(lmax+1)^2] s_lm at l*(lmax+1)+m
+    const double* gaunt;     // [(lmax+1)^3 (2lmax+1)] g_L(l1,l2,m) * gamma0_L at ((m*s1+l1)*s1+l2)*(2lmax+1)+L
+    int subtract_self;
+    double* out;             // [(lmax+1)^3][nb][nb]
+};
+hipError_t launch_export_nnn(const NnnArgs& a, hipStream_t s);
+
+struct AlmExportArgs {
+    const void* A;
+    int64_t ldA;
+    const int* perm;         // original index -> sorted index
+    int64_t p_begin;         // sorted index of the chunk's first primary
+    int64_t first, count;    // original indices
+    int nb, lmax;
+    const double* sign_scale;// [(lmax+1)^2] (-1)^m s_lm
+    int fp64;
+    double* out;
+};
+hipError_t launch_export_alm(const AlmExportArgs& a, hipStream_t s);
+
+}  // namespace tpcf

@@ -1,0 +1,243 @@
+"""Python binding of libtpcf.so (include/tpcf.h): argument marshalling only.
+
+Every step of the estimator runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors) and the stream. There is no fallback: if the
+library is missing this module raises.
+
+    h = Handle(box=1000.0, edges=np.linspace(20, 120, 11), lmax=10,
+               precision=PREC_MIXED_BF16X3)
+    out = h.run_catalogs(sizes, n_data, pos, None, mults)   # cuda tensors
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpcf.so")
+
+TPCF_OK = 0
+TPCF_ERR_ARG = -1
+TPCF_ERR_RANGE = -2
+TPCF_ERR_ALLOC = -3
+TPCF_ERR_DEVICE = -4
+TPCF_ERR_STATE = -5
+PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_MIXED_BF16X3 = 2
+PREC_MIXED_BF16X6 = 3
+F_KEEP_DEGENERATE = 1
+F_PAPER_LITERAL = 2
+
+EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
+           "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
+           "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_set_timing",
+           "tpcf_stage_times"]
+
+
+class TpcfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tpcf status {status}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double), ("nbins", ctypes.c_int32),
+                ("h_edges", ctypes.POINTER(ctypes.c_double)), ("lmax", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("grid_refine", ctypes.c_int32), ("workspace_limit", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libtpcf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run python -m paper_2408_03036_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    st = ctypes.c_int
+    lib.tpcf_create.argtypes = [ctypes.POINTER(Config), ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.tpcf_create.restype = st
+    lib.tpcf_destroy.argtypes = [vp]
+    lib.tpcf_destroy.restype = None
+    lib.tpcf_last_error.argtypes = [vp]
+    lib.tpcf_last_error.restype = ctypes.c_char_p
+    lib.tpcf_build_grid.argtypes = [vp, vp, vp, i64, i64]
+    lib.tpcf_build_grid.restype = st
+    lib.tpcf_alm_accumulate.argtypes = [vp]
+    lib.tpcf_alm_accumulate.restype = st
+    lib.tpcf_get_alm.argtypes = [vp, i64, i64, vp]
+    lib.tpcf_get_alm.restype = st
+    lib.tpcf_contract.argtypes = [vp, vp]
+    lib.tpcf_contract.restype = st
+    lib.tpcf_multipoles.argtypes = [vp, i32, vp, vp]
+    lib.tpcf_multipoles.restype = st
+    lib.tpcf_run_catalogs.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp]
+    lib.tpcf_run_catalogs.restype = st
+    lib.tpcf_sync.argtypes = [vp]
+    lib.tpcf_sync.restype = st
+    lib.tpcf_pair_count.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.tpcf_pair_count.restype = st
+    lib.tpcf_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.tpcf_set_timing.restype = st
+    lib.tpcf_stage_times.argtypes = [vp, i32, vp, vp]
+    lib.tpcf_stage_times.restype = st
+    _lib = lib
+    return lib
+
+
+def make_config(box, edges, lmax, precision=PREC_MIXED_BF16X3, flags=0, grid_refine=0,
+                workspace_limit=0):
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    cfg = Config(float(box), int(edges.shape[0] - 1),
+                 edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(lmax),
+                 int(precision), int(flags), int(grid_refine), int(workspace_limit))
+    return cfg, edges
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, name):
+    import torch
+    if t is None:
+        return
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+
+
+class Handle:
+    """Owns one tpcf_handle on a device and a stream."""
+
+    def __init__(self, box, edges, lmax, precision=PREC_MIXED_BF16X3, flags=0, grid_refine=0,
+                 workspace_limit=0, device=0, stream=None):
+        import torch
+        self.lib = load()
+        self.edges = np.ascontiguousarray(edges, dtype=np.float64)
+        self.nbins = self.edges.shape[0] - 1
+        self.lmax = int(lmax)
+        self.box = float(box)
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        cfg, _keep = make_config(box, self.edges, lmax, precision, flags, grid_refine,
+                                 workspace_limit)
+        h = ctypes.c_void_p()
+        rc = self.lib.tpcf_create(ctypes.byref(cfg), self.device,
+                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != TPCF_OK:
+            raise TpcfError(rc, "tpcf_create failed")
+        self.h = h
+
+    def _chk(self, rc):
+        if rc != TPCF_OK:
+            raise TpcfError(rc, self.lib.tpcf_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpcf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- steps ---------------------------------------------------------
+    def build_grid(self, pos, w=None, n_data=None):
+        import torch
+        _check_dev(pos, torch.float64, "pos")
+        _check_dev(w, torch.float64, "w")
+        n = pos.shape[0]
+        self._keep = (pos, w)
+        self._chk(self.lib.tpcf_build_grid(self.h, _ptr(pos), _ptr(w), n,
+                                           n if n_data is None else int(n_data)))
+
+    def alm_accumulate(self):
+        self._chk(self.lib.tpcf_alm_accumulate(self.h))
+
+    def get_alm(self, first, count):
+        import torch
+        s1 = self.lmax + 1
+        out = torch.empty((count, self.nbins, s1, s1, 2), dtype=torch.float64,
+                          device=f"cuda:{self.device}")
+        self._chk(self.lib.tpcf_get_alm(self.h, int(first), int(count), _ptr(out)))
+        return torch.view_as_complex(out)
+
+    def contract(self, export=False):
+        import torch
+        out = None
+        if export:
+            s1 = self.lmax + 1
+            out = torch.empty((s1, s1, s1, self.nbins, self.nbins), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        self._chk(self.lib.tpcf_contract(self.h, _ptr(out)))
+        return out
+
+    def multipoles(self, mults):
+        import torch
+        tr = np.ascontiguousarray(np.array(mults, dtype=np.int32).reshape(-1, 3))
+        out = torch.empty((tr.shape[0], self.nbins, self.nbins), dtype=torch.float64,
+                          device=f"cuda:{self.device}")
+        self._chk(self.lib.tpcf_multipoles(self.h, tr.shape[0], ctypes.c_void_p(tr.ctypes.data),
+                                           _ptr(out)))
+        return out
+
+    def run_catalogs(self, sizes, n_data, pos, w, mults, out=None):
+        import torch
+        _check_dev(pos, torch.float64, "pos")
+        _check_dev(w, torch.float64, "w")
+        sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+        nd = np.ascontiguousarray(np.asarray(n_data, dtype=np.int64))
+        tr = np.ascontiguousarray(np.array(mults, dtype=np.int32).reshape(-1, 3))
+        ncat = sizes.shape[0]
+        if out is None:
+            out = torch.empty((ncat, tr.shape[0], self.nbins, self.nbins), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        self._chk(self.lib.tpcf_run_catalogs(self.h, ncat, ctypes.c_void_p(sizes.ctypes.data),
+                                             ctypes.c_void_p(nd.ctypes.data), _ptr(pos), _ptr(w),
+                                             tr.shape[0], ctypes.c_void_p(tr.ctypes.data),
+                                             _ptr(out)))
+        return out
+
+    def sync(self):
+        self._chk(self.lib.tpcf_sync(self.h))
+
+    def pair_count(self):
+        v = ctypes.c_int64(0)
+        self._chk(self.lib.tpcf_pair_count(self.h, ctypes.byref(v)))
+        return int(v.value)
+
+    def set_timing(self, enable=True):
+        self._chk(self.lib.tpcf_set_timing(self.h, 1 if enable else 0))
+
+    def stage_times(self):
+        ms = np.zeros(5)
+        nl = np.zeros(5, dtype=np.int64)
+        self._chk(self.lib.tpcf_stage_times(self.h, 5, ctypes.c_void_p(ms.ctypes.data),
+                                            ctypes.c_void_p(nl.ctypes.data)))
+        return ms, nl
+
+
+def estimate(pos, box, edges, lmax, mults, w=None, n_data=None, precision=PREC_MIXED_BF16X3,
+             flags=0, grid_refine=0):
+    """One catalogue through the four steps; returns the multipoles tensor."""
+    h = Handle(box, edges, lmax, precision=precision, flags=flags, grid_refine=grid_refine,
+               device=pos.device.index or 0)
+    h.build_grid(pos, w, n_data)
+    h.alm_accumulate()
+    h.contract()
+    out = h.multipoles(mults)
+    h.sync()
+    h.close()
+    return out

@@ -1,0 +1,87 @@
+"""C-ABI checks that need no GPU: the library builds/loads, exports every
+symbol include/tpcf.h declares, and rejects invalid configurations before any
+device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2408_03036_amd import tpcf as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tpcf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpcf_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        from paper_2408_03036_amd import build
+        build.build()
+    return T.load()
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(T.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _create(lib, **kw):
+    args = dict(box=200.0, edges=np.linspace(0.0, 40.0, 9), lmax=4)
+    args.update(kw)
+    cfg, keep = T.make_config(**args)
+    h = ctypes.c_void_p()
+    rc = lib.tpcf_create(ctypes.byref(cfg), 0, None, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(box=0.0), T.TPCF_ERR_ARG),
+    (dict(box=float("nan")), T.TPCF_ERR_ARG),
+    (dict(box=-5.0), T.TPCF_ERR_ARG),
+    (dict(edges=[0.0, 10.0, 10.0]), T.TPCF_ERR_RANGE),
+    (dict(edges=[5.0, 4.0, 10.0]), T.TPCF_ERR_RANGE),
+    (dict(edges=[-1.0, 10.0]), T.TPCF_ERR_RANGE),
+    (dict(edges=[0.0, 101.0]), T.TPCF_ERR_RANGE),
+    (dict(lmax=13), T.TPCF_ERR_RANGE),
+    (dict(lmax=-1), T.TPCF_ERR_RANGE),
+    (dict(precision=4), T.TPCF_ERR_ARG),
+    (dict(lmax=12, edges=np.linspace(0, 40, 33), precision=2), T.TPCF_ERR_RANGE),
+    (dict(grid_refine=5), T.TPCF_ERR_RANGE),
+    (dict(flags=8), T.TPCF_ERR_ARG),
+    (dict(edges=np.linspace(0, 40, 34)), T.TPCF_ERR_RANGE),
+])
+def test_invalid_configs_rejected_before_device(lib, kw, expect):
+    rc, h = _create(lib, **kw)
+    assert rc == expect
+    assert not h.value
+
+
+def test_null_arguments(lib):
+    cfg, keep = T.make_config(200.0, np.linspace(0, 40, 9), 4)
+    assert lib.tpcf_create(ctypes.byref(cfg), 0, None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_create(None, 0, None, ctypes.byref(ctypes.c_void_p())) == T.TPCF_ERR_ARG
+    # calls on a NULL handle fail cleanly
+    assert lib.tpcf_build_grid(None, None, None, 10, 10) == T.TPCF_ERR_ARG
+    assert lib.tpcf_alm_accumulate(None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_sync(None) == T.TPCF_ERR_ARG
+    assert b"invalid" in lib.tpcf_last_error(None)
+    lib.tpcf_destroy(None)
+
+
+def test_valid_config_without_gpu_reports_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h = _create(lib)
+    assert rc == T.TPCF_ERR_DEVICE

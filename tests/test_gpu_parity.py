@@ -1,0 +1,266 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances, relative to max |zeta| over all multipoles and bins:
+FP64 path 1e-12, FP32 path 1e-5, split-BF16 (3 products) 1e-4, split-BF16
+(6 products) 1e-5. Pair counts and lmax = 0 integer triplet counts are exact.
+
+The 3-product split keeps x to 2^-16 relative, and the removal of degenerate
+triangles on b1 = b2 cancels sum_p |a|^2 against sum_p sum_j |Y|^2, so its
+error grows like 2^-16 (2l+1) / nbar_b (nbar_b = neighbours per primary in
+bin b). Its 1e-4 bound is checked on the dense configuration it is meant for;
+the sparse C1 anchor (0.13 neighbours per primary in its first bin) is
+checked with the 6-product split.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2408_03036_amd import catalogs as C
+from paper_2408_03036_amd import tpcf as T
+
+pytestmark = pytest.mark.gpu
+
+TOL = {T.PREC_FP64: 1e-12, T.PREC_FP32: 1e-5, T.PREC_MIXED_BF16X3: 1e-4,
+       T.PREC_MIXED_BF16X6: 1e-5}
+PRECS = [T.PREC_FP64, T.PREC_FP32, T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6]
+PNAME = {T.PREC_FP64: "fp64", T.PREC_FP32: "fp32", T.PREC_MIXED_BF16X3: "bf16x3",
+         T.PREC_MIXED_BF16X6: "bf16x6"}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    T.load()
+    return _t
+
+
+def gpu(torch, a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def run_gpu(torch, pos, box, edges, lmax, mults, prec, w=None, n_data=None, flags=0, refine=0,
+            want_alm=False, want_nnn=False):
+    say(f"  gpu: n={pos.shape[0]} box={box} nb={len(edges) - 1} lmax={lmax} prec={PNAME[prec]} "
+        f"refine={refine} weighted={w is not None}")
+    h = T.Handle(box, edges, lmax, precision=prec, flags=flags, grid_refine=refine)
+    P = gpu(torch, pos)
+    W = gpu(torch, w)
+    h.build_grid(P, W, n_data)
+    h.alm_accumulate()
+    alm = h.get_alm(0, pos.shape[0]).cpu().numpy() if want_alm else None
+    nnn = h.contract(export=want_nnn)
+    out = h.multipoles(mults)
+    h.sync()
+    npairs = h.pair_count()
+    res = out.cpu().numpy()
+    nnn = nnn.cpu().numpy() if nnn is not None else None
+    h.close()
+    return res, npairs, alm, nnn
+
+
+def rel_err(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+C1 = dict(n=2000, box=200.0, edges=np.linspace(0.0, 40.0, 9), lmax=4, Lmax=2)
+
+
+@pytest.fixture(scope="module")
+def c1_case():
+    pos = C.poisson(C1["n"], C1["box"], C.catalogue_seed(0))
+    mults = O.all_multipoles(C1["lmax"], C1["Lmax"])
+    re, im, res = O.run(pos, C1["box"], C1["edges"], C1["lmax"], mults)
+    return pos, mults, re, res
+
+
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32, T.PREC_MIXED_BF16X6])
+def test_c1_multipoles_match_oracle(torch, c1_case, prec):
+    pos, mults, ref, res = c1_case
+    got, npairs, _, _ = run_gpu(torch, pos, C1["box"], C1["edges"], C1["lmax"], mults, prec)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  C1 {PNAME[prec]} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+# Dense anchor: 10^4 clustered points in a 400 Mpc/h box (mean density
+# 1.56e-4, close to the 400k-in-1500 catalogue), 12 bins over [10, 130],
+# lmax = 10, L <= 4.
+DENSE = dict(n=10000, box=400.0, edges=np.linspace(10.0, 130.0, 13), lmax=10, Lmax=4)
+
+
+@pytest.fixture(scope="module")
+def dense_case():
+    pos = C.zeldovich(DENSE["n"], DENSE["box"], 5.0, 0.8, C.catalogue_seed(3), grid=64)
+    mults = O.all_multipoles(DENSE["lmax"], DENSE["Lmax"])
+    say("  oracle: dense anchor")
+    re, im, res = O.run(pos, DENSE["box"], DENSE["edges"], DENSE["lmax"], mults)
+    return pos, mults, re, res
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_dense_multipoles_match_oracle(torch, dense_case, prec):
+    pos, mults, ref, res = dense_case
+    got, npairs, _, _ = run_gpu(torch, pos, DENSE["box"], DENSE["edges"], DENSE["lmax"], mults,
+                                prec)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  dense {PNAME[prec]} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
+def test_alm_and_nnn_match_oracle(torch, prec):
+    box, edges, lmax = 100.0, np.array([4.0, 9.0, 14.0, 20.0, 25.0]), 6
+    pos = C.zeldovich(3000, box, 2.0, 0.8, 77, grid=32)
+    res = O.estimate(pos, box, edges, lmax, want_alm=True)
+    mults = O.all_multipoles(lmax, 2)
+    _, npairs, alm, nnn = run_gpu(torch, pos, box, edges, lmax, mults, prec, want_alm=True,
+                                  want_nnn=True)
+    assert npairs == res.npairs
+    s1 = lmax + 1
+    mask = np.tril(np.ones((s1, s1), dtype=bool))  # m <= l
+    ea = np.abs(alm[..., mask] - res.alm[..., mask]).max() / np.abs(res.alm).max()
+    say(f"  a_lm {PNAME[prec]} rel err {ea:.3e}")
+    assert ea < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+    ref = res.nnn.real
+    en = np.abs(nnn - ref).max() / np.abs(ref).max()
+    say(f"  NNN {PNAME[prec]} rel err {en:.3e}")
+    assert en < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_weighted_data_minus_randoms(torch, prec):
+    box, edges, lmax = 60.0, np.array([2.0, 5.0, 8.0, 12.0]), 3
+    nd, nr = 400, 800
+    pos = np.vstack([C.zeldovich(nd, box, 1.5, 0.8, 91, grid=16), C.randoms(nr, box, 92)])
+    w = C.dr_weights(nd, nr)
+    mults = O.all_multipoles(lmax, 3)
+    ref, _, res = O.run(pos, box, edges, lmax, mults, w=w, n_data=nd)
+    got, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec, w=w, n_data=nd)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  D-R {PNAME[prec]} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_single_cell_box_and_bins_from_zero(torch, prec):
+    """rmax close to L/2: one cell with per-pair minimum image; first bin from 0."""
+    box, edges, lmax = 10.0, np.array([0.0, 1.5, 3.0, 4.9]), 4
+    pos = C.poisson(300, box, 101)
+    mults = O.all_multipoles(lmax, 4)
+    ref, _, res = O.run(pos, box, edges, lmax, mults)
+    got, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  single-cell {PNAME[prec]} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("refine", [1, 2, 3])
+def test_lmax0_exact_counts_every_grid(torch, refine):
+    """lmax = 0: integer triplet counts, exact on every precision path and
+    every neighbour-grid refinement (pins the pair set and the binning)."""
+    box, edges = 120.0, np.linspace(5.0, 30.0, 6)
+    pos = C.zeldovich(4000, box, 3.0, 0.8, 111, grid=32)
+    ref, _, res = O.run(pos, box, edges, 0, [(0, 0, 0)])
+    for prec in PRECS:
+        got, npairs, _, _ = run_gpu(torch, pos, box, edges, 0, [(0, 0, 0)], prec, refine=refine)
+        assert npairs == res.npairs
+        err = rel_err(got, ref)
+        assert err < 1e-12, (PNAME[prec], err)
+
+
+def test_lattice_ties_on_bin_edges(torch):
+    """Dyadic lattice: many pairs exactly on bin edges (half-open bins)."""
+    box, edges = 16.0, np.array([0.5, 1.0, 1.5, 2.0, 3.0])
+    pos = np.unique(C.dyadic_lattice(1500, box, 5, 121), axis=0)
+    for lmax in (0, 3):
+        mults = O.all_multipoles(lmax, 2)
+        ref, _, res = O.run(pos, box, edges, lmax, mults)
+        for prec in PRECS:
+            got, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec)
+            assert npairs == res.npairs, PNAME[prec]
+            assert rel_err(got, ref) < TOL[prec], PNAME[prec]
+
+
+def test_keep_degenerate_and_literal_flags(torch):
+    box, edges, lmax = 50.0, np.array([2.0, 6.0, 10.0]), 3
+    pos = C.poisson(600, box, 131)
+    mults = O.all_multipoles(lmax, 2)
+    ref_keep, _, _ = O.run(pos, box, edges, lmax, mults, subtract_self=False)
+    got, _, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, T.PREC_FP64,
+                           flags=T.F_KEEP_DEGENERATE)
+    assert rel_err(got, ref_keep) < 1e-12
+    ref_lit, _, _ = O.run(pos, box, edges, lmax, mults, literal=True)
+    got, _, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, T.PREC_FP64,
+                           flags=T.F_PAPER_LITERAL)
+    assert rel_err(got, ref_lit) < 1e-12
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_equals_single_bitwise(torch, prec):
+    box, edges, lmax = 150.0, np.linspace(10.0, 40.0, 4), 4
+    sizes = [1500, 700, 2600]
+    cats = [C.zeldovich(n, box, 3.0, 0.8, 200 + i, grid=32) for i, n in enumerate(sizes)]
+    mults = O.all_multipoles(lmax, 2)
+    h = T.Handle(box, edges, lmax, precision=prec)
+    say(f"  batched {PNAME[prec]}")
+    P = gpu(torch, np.vstack(cats))
+    out = h.run_catalogs(sizes, sizes, P, None, mults)
+    h.sync()
+    out2 = h.run_catalogs(sizes, sizes, P, None, mults)
+    h.sync()
+    batched = out.cpu().numpy()
+    assert np.array_equal(batched, out2.cpu().numpy()), "run-to-run difference"
+    for i, cat in enumerate(cats):
+        single, _, _, _ = run_gpu(torch, cat, box, edges, lmax, mults, prec)
+        assert np.array_equal(batched[i], single), i
+        ref, _, _ = O.run(cat, box, edges, lmax, mults)
+        assert rel_err(single, ref) < TOL[prec]
+    h.close()
+
+
+def test_nonfinite_positions_reported(torch):
+    pos = C.poisson(500, 50.0, 141)
+    pos[17, 1] = np.nan
+    h = T.Handle(50.0, np.array([1.0, 5.0]), 2, precision=T.PREC_FP32)
+    h.build_grid(gpu(torch, pos))
+    with pytest.raises(T.TpcfError) as e:
+        h.alm_accumulate()
+    assert e.value.status == T.TPCF_ERR_DEVICE
+    h.close()
+
+
+def test_out_of_order_calls(torch):
+    h = T.Handle(50.0, np.array([1.0, 5.0]), 2)
+    with pytest.raises(T.TpcfError) as e:
+        h.alm_accumulate()
+    assert e.value.status == T.TPCF_ERR_STATE
+    with pytest.raises(T.TpcfError) as e:
+        h.multipoles([(0, 0, 0)])
+    assert e.value.status == T.TPCF_ERR_STATE
+    with pytest.raises(T.TpcfError) as e:
+        h.multipoles([(1, 0, 0)])
+    assert e.value.status == T.TPCF_ERR_ARG
+    h.close()
+
+
+def test_workspace_limit_enforced(torch):
+    pos = C.poisson(20000, 100.0, 151)
+    h = T.Handle(100.0, np.linspace(2.0, 20.0, 10), 10, workspace_limit=1 << 20)
+    with pytest.raises(T.TpcfError) as e:
+        h.build_grid(gpu(torch, pos))
+        h.alm_accumulate()
+    assert e.value.status == T.TPCF_ERR_ALLOC
+    h.close()
