@@ -62,11 +62,10 @@ struct tpcf_handle_s {
     // constants
     std::vector<double> e2, vol, scale, sign_scale, gamma0;
     std::vector<float> e2f, guard;
-    std::vector<unsigned char> lut;
     std::vector<double> q;  // q[((l1*s1+l2)*s1+m)*(2lmax+1)+L]
     std::vector<int64_t> goff;
     int64_t gsize = 0;
-    DevBuf d_e2, d_e2f, d_guard, d_lut, d_runs, d_shift_f, d_goff, d_vol, d_scale, d_sign_scale,
+    DevBuf d_e2, d_e2f, d_guard, d_runs, d_shift_f, d_goff, d_vol, d_scale, d_sign_scale,
         d_gaunt;
 
     // grid of the current group
@@ -79,13 +78,17 @@ struct tpcf_handle_s {
     std::vector<double> n_data;
     bool unit_w = true;
     DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pd, d_perm,
-        d_catid, d_flag;
+        d_catid, d_flag, d_istart, d_icell, d_icat;
+    std::vector<int> item_cat;       // [ncat+1] first work item of each catalogue
 
     // pair pass
     std::vector<int64_t> sub_start;  // global subchunks (sorted index of first primary), + end
     std::vector<int> cat_sub;        // [ncat+1]
     std::vector<Chunk> chunks;
     int64_t kc = 4096;
+    int uniform = 0;      // bins equally spaced in r
+    float inv_dr = 0.f;   // 1 / bin width (uniform bins)
+    float delta = 0.f;    // FP32 guard band in units of the bin width
     int64_t chunk_cap = 0;
     unsigned long long list_cap = 0;
     DevBuf d_list, d_lcursor, d_boff, d_cnt, d_A, d_subs, d_catsub, d_part, d_pself, d_G, d_S, d_nd,
@@ -304,14 +307,6 @@ tpcf_status setup_constants(tpcf_handle h) {
     for (int b = 0; b < nb; ++b)
         h->vol[b] = 4.0 * kPi / 3.0 *
                     (h->edges[b + 1] * h->edges[b + 1] * h->edges[b + 1] - h->edges[b] * h->edges[b] * h->edges[b]);
-    h->lut.resize(kLut);
-    const double span = h->e2[nb] - h->e2[0];
-    for (int i = 0; i < kLut; ++i) {
-        const double r2 = h->e2[0] + span * i / kLut;
-        int b = 0;
-        while (b + 1 < nb && r2 >= h->e2[b + 1]) ++b;
-        h->lut[i] = (unsigned char)b;
-    }
     h->scale.assign((size_t)s1 * s1, 0.0);
     h->sign_scale.assign((size_t)s1 * s1, 0.0);
     for (int l = 0; l <= lmax; ++l)
@@ -343,7 +338,6 @@ tpcf_status setup_constants(tpcf_handle h) {
     tpcf_status st;
     if ((st = upload(h, h->d_e2, h->e2.data(), sizeof(double) * (nb + 1))) != TPCF_OK) return st;
     if ((st = upload(h, h->d_e2f, h->e2f.data(), sizeof(float) * (nb + 1))) != TPCF_OK) return st;
-    if ((st = upload(h, h->d_lut, h->lut.data(), kLut)) != TPCF_OK) return st;
     if ((st = upload(h, h->d_goff, h->goff.data(), sizeof(int64_t) * (lmax + 2))) != TPCF_OK) return st;
     if ((st = upload(h, h->d_vol, h->vol.data(), sizeof(double) * nb)) != TPCF_OK) return st;
     if ((st = upload(h, h->d_scale, h->scale.data(), sizeof(double) * s1 * s1)) != TPCF_OK) return st;
@@ -444,7 +438,8 @@ tpcf_status plan_grid(tpcf_handle h, int64_t max_cat) {
         sh[3 * c + 2] = (float)(oz * h->g.h);
     }
     // guard bands of the FP32 binning: bound of the single-precision error of
-    // r^2 for pairs inside the stencil (see DESIGN notes in the kernel file)
+    // r^2 for pairs inside the stencil: rounding of the cell-relative inputs,
+    // of the separations and of r^2 itself, with a factor 4 of margin
     const double span = h->g.single ? L : (k + 1) * h->g.h;
     const double dd = 4.0 * ulp32(span);
     h->guard.resize(h->nb + 1);
@@ -452,6 +447,27 @@ tpcf_status plan_grid(tpcf_handle h, int64_t max_cat) {
         const double e = h->edges[b];
         const double gb = 4.0 * (2.0 * std::sqrt(3.0) * std::max(e, dd) * dd + 4.0 * std::ldexp(e * e, -24) + 3.0 * dd * dd);
         h->guard[b] = (float)gb;
+    }
+    // Equally spaced bins are found as floor((r - e0) / dr) in FP32; the
+    // guard band becomes a band of width delta (in bin units) around each
+    // integer, covering the error of r^2 above plus that of the square root,
+    // of e0 and 1/dr in FP32.
+    {
+        const int nb = h->nb;
+        const double e0 = h->edges[0], dr = (h->edges[nb] - e0) / nb;
+        bool uni = true;
+        for (int b = 0; b <= nb; ++b)
+            if (std::fabs(h->edges[b] - (e0 + b * dr)) > 1e-12 * h->edges[nb]) uni = false;
+        double gmax = 0.0;
+        for (int b = 0; b <= nb; ++b) {
+            const double g2 = h->guard[b];
+            gmax = std::max(gmax, g2 / (h->edges[b] + std::sqrt(g2)));
+        }
+        const double eps = 2.0 * gmax / dr + 4.0 * (ulp32(h->edges[nb]) + ulp32(std::max(e0, 1e-30))) / dr +
+                           8.0 * ulp32((double)nb + 1.0);
+        h->uniform = uni && eps < 0.05 ? 1 : 0;
+        h->inv_dr = (float)(1.0 / dr);
+        h->delta = (float)eps;
     }
     tpcf_status st;
     if ((st = upload(h, h->d_runs, h->runs.data(), sizeof(StencilRun) * h->runs.size())) != TPCF_OK) return st;
@@ -507,7 +523,19 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     HIPCHK(launch_grid_fill(d_pos, d_w, N, P<int>(h->d_orig), P<int>(h->d_cellid), h->g, P<float4>(h->d_pf),
                             P<float>(h->d_pw), P<double4>(h->d_pd), P<int>(h->d_perm), P<int>(h->d_catid),
                             h->stream));
+    // work items of the binning pass: blocks of up to kItemPrims primaries of one cell
+    const int64_t nitems_max = M + N / kItemPrims + 1;
+    if ((st = ensure(h, h->d_istart, sizeof(int) * (M + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_icell, sizeof(int) * nitems_max)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_icat, sizeof(int) * (h->ncat + 1))) != TPCF_OK) return st;
+    HIPCHK(launch_items_count(P<int>(h->d_start), M, P<int>(h->d_cursor), h->stream));
+    HIPCHK(launch_grid_scan(P<int>(h->d_cursor), M, P<int>(h->d_istart), h->stream));
+    HIPCHK(launch_items_fill(P<int>(h->d_istart), M, P<int>(h->d_icell), h->stream));
+    HIPCHK(launch_items_cat(P<int>(h->d_istart), h->ncat, h->g.ncell, P<int>(h->d_icat), h->stream));
     t_end(h, t);
+    h->item_cat.assign(h->ncat + 1, 0);
+    HIPCHK(hipMemcpyAsync(h->item_cat.data(), P<int>(h->d_icat), sizeof(int) * (h->ncat + 1),
+                          hipMemcpyDeviceToHost, h->stream));
     return TPCF_OK;
 }
 
@@ -560,7 +588,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     if ((st = ensure(h, h->d_cnt, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_A, (size_t)h->nb * h->NV * h->ldA * elem)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_list, sizeof(uint32_t) * h->list_cap)) != TPCF_OK) return st;
-    if ((st = ensure(h, h->d_lcursor, 64)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_lcursor, sizeof(unsigned long long) * kSlots * 16)) != TPCF_OK) return st;
     // subchunk tables: per chunk, chunk-relative starts are uploaded on demand
     if ((st = ensure(h, h->d_subs, sizeof(int) * (nsub + 1) + 64)) != TPCF_OK) return st;
     if ((st = upload(h, h->d_catsub, h->cat_sub.data(), sizeof(int) * (h->ncat + 1))) != TPCF_OK) return st;
@@ -577,7 +605,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     // the table is chunk-specific; the copy is stream-ordered before its use
     if ((st = upload(h, h->d_subs, rel.data(), sizeof(int) * rel.size())) != TPCF_OK) return st;
     for (int attempt = 0; attempt < 6; ++attempt) {
-        HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), 1, 0ull, h->stream));
+        HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), kSlots * 16, 0ull, h->stream));
         HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 1, 0, h->stream));
         BinArgs b{};
         b.pf = P<float4>(h->d_pf);
@@ -592,8 +620,6 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         b.e2 = P<double>(h->d_e2);
         b.e2f = P<float>(h->d_e2f);
         b.guard = P<float>(h->d_guard);
-        b.lut = P<unsigned char>(h->d_lut);
-        b.lut_scale = (float)(kLut / (h->e2[h->nb] - h->e2[0]));
         b.p_begin = ch.p_begin;
         b.p_end = ch.p_end;
         b.list = P<uint32_t>(h->d_list);
@@ -602,7 +628,23 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         b.boff = P<uint32_t>(h->d_boff);
         b.cnt = P<uint32_t>(h->d_cnt);
         b.overflow = P<int>(h->d_flag) + 1;
-        b.fp64 = h->fp64;
+        b.npmax = 2 * (int)h->runs.size();
+        b.uniform = h->uniform;
+        b.e0f = (float)h->edges[0];
+        b.inv_dr = h->inv_dr;
+        b.delta = h->delta;
+        b.inv_boxf = (float)(1.0 / h->g.box);
+        b.item_start = P<int>(h->d_istart);
+        b.item_cell = P<int>(h->d_icell);
+        {
+            // work items of the catalogues holding the chunk's primaries
+            int c0 = 0, c1 = 0;
+            while (c0 + 1 < h->ncat && h->pt_off[c0 + 1] <= ch.p_begin) ++c0;
+            c1 = c0;
+            while (c1 + 1 < h->ncat && h->pt_off[c1 + 1] < ch.p_end) ++c1;
+            b.item_lo = h->item_cat[c0];
+            b.item_hi = h->item_cat[c1 + 1];
+        }
         Timer t;
         t_begin(h, 1, t);
         HIPCHK(launch_pair_bin(b, h->stream));
@@ -834,7 +876,7 @@ void tpcf_destroy(tpcf_handle h) {
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
     }
-    DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_lut, &h->d_runs, &h->d_shift_f, &h->d_goff,
+    DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_runs, &h->d_shift_f, &h->d_goff,
                      &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
                      &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
                      &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_lcursor, &h->d_boff,

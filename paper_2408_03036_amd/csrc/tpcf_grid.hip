@@ -145,9 +145,46 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
     if (i < n) p[i] = v;
 }
 
+// Work items of the binning pass: cell c holds ceil(count / kItemPrims) items.
+__global__ void k_items_count(const int* __restrict__ cell_start, int64_t m, int* __restrict__ nitems) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    const int n = cell_start[c + 1] - cell_start[c];
+    nitems[c] = (n + kItemPrims - 1) / kItemPrims;
+}
+
+__global__ void k_items_fill(const int* __restrict__ item_start, int64_t m, int* __restrict__ item_cell) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    for (int i = item_start[c]; i < item_start[c + 1]; ++i) item_cell[i] = (int)c;
+}
+
+__global__ void k_items_cat(const int* __restrict__ item_start, int ncat, int ncell, int* __restrict__ item_cat) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c <= ncat) item_cat[c] = item_start[(int64_t)c * ncell];
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t launch_items_count(const int* cell_start, int64_t m, int* nitems, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_items_count, dim3(nblk(m, 256)), dim3(256), 0, s, cell_start, m, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_items_fill(const int* item_start, int64_t m, int* item_cell, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_items_fill, dim3(nblk(m, 256)), dim3(256), 0, s, item_start, m, item_cell);
+    return hipGetLastError();
+}
+
+hipError_t launch_items_cat(const int* item_start, int ncat, int ncell, int* item_cat, hipStream_t s) {
+    hipLaunchKernelGGL(k_items_cat, dim3(nblk(ncat + 1, 256)), dim3(256), 0, s, item_start, ncat, ncell,
+                       item_cat);
+    return hipGetLastError();
+}
 
 hipError_t launch_grid_assign(const double* pos, const double*, int64_t n, const int64_t* pt_off,
                               int ncat, Grid g, int* cellid, int* count, int* nonfinite,

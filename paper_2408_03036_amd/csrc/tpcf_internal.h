@@ -61,6 +61,11 @@ hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const
                             const int* cellid, Grid g, float4* pf, float* pw, double4* pd,
                             int* perm, int* catid, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
+// Work items of the binning pass: each cell's primaries in blocks of kItemPrims.
+constexpr int kItemPrims = 32;
+hipError_t launch_items_count(const int* cell_start, int64_t m, int* nitems, hipStream_t s);
+hipError_t launch_items_fill(const int* item_start, int64_t m, int* item_cell, hipStream_t s);
+hipError_t launch_items_cat(const int* item_start, int ncat, int ncell, int* item_cat, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 
 // Pair pass (tpcf_pairs.hip)
@@ -77,19 +82,25 @@ struct BinArgs {
     const double* e2;        // [nb+1] squared edges (FP64)
     const float* e2f;        // [nb+1] squared edges (FP32)
     const float* guard;      // [nb+1] FP32 guard band around each squared edge
-    const unsigned char* lut;// [kLut] bin lookup over squared separation
-    float lut_scale;         // kLut / (e2[nb] - e2[0])
     int64_t p_begin, p_end;  // primaries (sorted indices) of this chunk
     uint32_t* list;          // hit lists of the chunk
-    unsigned long long* cursor; // [1] bump allocator in `list`
+    unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each
     unsigned long long capacity;
     uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists
     uint32_t* cnt;           // [(p_end-p_begin)*nb] lengths
     int* overflow;           // [1] set when `list` is too small
-    int fp64;                // exact FP64 binning for every pair (plain FP64 path)
+    int npmax;               // capacity of the piece table (>= 2 nruns)
+    int uniform;             // bins equally spaced in r: bin = floor((r - e0) / dr)
+    float e0f, inv_dr;       // FP32 first edge and 1 / bin width (uniform bins)
+    float delta;             // guard band in units of the bin width (uniform bins)
+    float inv_boxf;          // 1 / L (single-cell mode)
+    const int* item_start;   // [ncat*ncell+1] first work item of each cell
+    const int* item_cell;    // [items] cell of each work item
+    int64_t item_lo, item_hi;// work items of the catalogues holding the chunk's primaries
 };
-constexpr int kLut = 1024;
+constexpr int kSlots = 256;  // list allocation cursors (each on its own 128-byte line)
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);
+size_t pair_bin_lds_bytes(int npmax);
 
 struct AlmArgs {
     const float4* pf;

@@ -3,12 +3,13 @@
 // radial bin b, accumulate w_j conj(Y_lm(rhat_pj)) into a_lm(p, b).
 //
 // Two kernels:
-//  k_pair_bin  one wavefront per primary. Lanes walk the primary's stencil of
-//              neighbour cells as one flattened candidate range (coalesced
-//              loads of the cell-sorted points), test the separation, find the
-//              bin and collect the hits in LDS. The hits are then written to a
-//              per-primary list sorted by bin (stable, so the accumulation
-//              order is deterministic), with (offset, count) per (p, b).
+//  k_pair_bin  one workgroup per work item (up to 32 primaries of one cell of
+//              the neighbour grid). The cell's stencil of neighbour cells is
+//              one flattened candidate range, staged tile by tile in LDS in the
+//              home cell's frame; every wavefront tests the tile against its
+//              primaries. A first sweep counts the hits per (p, b), a second
+//              writes each hit straight to a per-primary list laid out bin by
+//              bin, with (offset, count) per (p, b).
 //  k_pair_alm  lane = one (primary, bin) list. A wavefront holds 64
 //              consecutive primaries of one bin; each lane walks its list and
 //              accumulates every harmonic in registers, so no cross-lane
@@ -33,8 +34,6 @@ namespace tpcf {
 
 namespace {
 
-constexpr int kHB = 2048;  // hits a wavefront can sort in LDS per pass
-
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 
 __device__ inline int lanes_below(uint64_t mask) {
@@ -49,74 +48,96 @@ __device__ inline void wave_sync() {
 
 // XCD-aware block remap: the hardware hands consecutive workgroups to the 8
 // XCDs in turn; this gives every XCD a contiguous range of logical blocks so
-// that neighbouring primaries share that XCD's L2.
+// that neighbouring primaries share that XCD's L2. The map is a permutation
+// of [0, nblocks) when nblocks is a multiple of 8; launches round up to that.
 __device__ inline int64_t xcd_block(int64_t bid, int64_t nblocks) {
     int64_t per = (nblocks + 7) / 8;
     return (bid % 8) * per + bid / 8;
 }
 
-struct RunLds {
-    int start[kMaxRuns];
-    int pref[kMaxRuns + 1];
-    float sx[kMaxRuns], sy[kMaxRuns], zo[kMaxRuns];
-    int code[kMaxRuns];   // (ox+k)*(2k+1)+(oy+k): z offset is added per candidate
-    int wrap[kMaxRuns];   // wrap signs, 2 bits per axis (x: bits 0-1, y: 2-3, z: 4-5), value+1
-    int n;
+// Bin tables shared by the workgroup.
+struct BinTables {
+    double e2[kMaxBins + 1];
+    float e2f[kMaxBins + 1];
+    float guard[kMaxBins + 1];
 };
 
-struct BinLds {
-    RunLds r;
-    uint32_t buf[kHB];
-    unsigned char bbuf[kHB];
-    int cnt[kMaxBins];
-    int pre[kMaxBins];
+// Candidate table of a home cell in LDS. Pieces are runs of consecutive cells
+// of the cell's stencil, flattened into one candidate range [0, pref[n]).
+//   rec[r]  = (j offset = start - pref, sx, sy, zo): candidate g of piece r is
+//             point g + off, shifted into the home cell's frame by
+//             (sx, sy, (izf + zo) h), izf = the candidate's cell z index;
+//   code[r] = ((ox+k)(2k+1) + (oy+k))(2k+1) + k | wrap << 16, wrap = the
+//             periodic shift signs (+1) of x, y, z in 2-bit fields.
+struct Pieces {
+    float4* rec;
+    int* pref;
+    int* code;
+    int* n;
 };
+
+__host__ __device__ inline size_t pieces_lds_bytes(int npmax) {
+    size_t b = sizeof(float4) * (size_t)npmax + sizeof(int) * (size_t)(2 * npmax + 1) + sizeof(int) * 4;
+    return (b + 15) / 16 * 16;
+}
+
+__device__ inline Pieces pieces_view(unsigned char* base, int npmax) {
+    Pieces w;
+    w.rec = reinterpret_cast<float4*>(base);
+    w.pref = reinterpret_cast<int*>(w.rec + npmax);
+    w.code = w.pref + npmax + 1;
+    w.n = w.code + npmax;
+    return w;
+}
 
 __device__ inline double wrap_shift(int bits, int axis, double L) {
     return (double)(((bits >> (2 * axis)) & 3) - 1) * L;
 }
 
-// Exact FP64 bin of a pair (the reference evaluation), -1 if outside the
-// shells or at zero separation. Shifts come from the cell geometry (equal to
-// the minimum image for any pair inside the shells) or, in single-cell mode,
+// Exact FP64 bin of a pair (the reference evaluation: r^2 = dx*dx + dy*dy +
+// dz*dz in that order, no fused multiply-add), -1 outside the shells or at
+// zero separation. Periodic shifts come from the cell geometry (equal to the
+// minimum image for any pair inside the shells) or, in single-cell mode,
 // from rint.
-__device__ inline int exact_bin(const double4& P, const double4& Q, int wbits, const BinArgs& a) {
+// Takes its few parameters by value: out of line, the rare call costs the
+// hot loop no registers and copies no argument block to scratch.
+template <bool SINGLE>
+__device__ __noinline__ int exact_bin_t(const double4 P, const double4 Q, int wbits, double box, int nb,
+                                        const double* e2) {
 #pragma clang fp contract(off)
     double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-    if (a.g.single) {
-        dx -= a.g.box * rint(dx / a.g.box);
-        dy -= a.g.box * rint(dy / a.g.box);
-        dz -= a.g.box * rint(dz / a.g.box);
+    if constexpr (SINGLE) {
+        dx -= box * rint(dx / box);
+        dy -= box * rint(dy / box);
+        dz -= box * rint(dz / box);
     } else {
-        dx += wrap_shift(wbits, 0, a.g.box);
-        dy += wrap_shift(wbits, 1, a.g.box);
-        dz += wrap_shift(wbits, 2, a.g.box);
+        dx += wrap_shift(wbits, 0, box);
+        dy += wrap_shift(wbits, 1, box);
+        dz += wrap_shift(wbits, 2, box);
     }
     double r2 = dx * dx;
     r2 += dy * dy;
     r2 += dz * dz;
-    if (r2 == 0.0 || r2 < a.e2[0] || r2 >= a.e2[a.nb]) return -1;
-    int b = a.lut[min(kLut - 1, max(0, (int)((float)(r2 - a.e2[0]) * a.lut_scale)))];
-    while (b + 1 < a.nb && r2 >= a.e2[b + 1]) ++b;
-    while (b > 0 && r2 < a.e2[b]) --b;
+    if (r2 == 0.0 || r2 < e2[0] || r2 >= e2[nb]) return -1;
+    int b = 0;
+    while (b + 1 < nb && r2 >= e2[b + 1]) ++b;
     return b;
 }
 
-// Builds the flattened candidate ranges of primary p (cell cx,cy,cz) in LDS.
+// Builds the flattened candidate ranges of the primary in cell (cx,cy,cz).
 // Every stencil run (fixed ox, oy; oz in [oz_lo, oz_hi]) becomes at most two
 // pieces of consecutive cells: the part that wraps through the z boundary and
 // the part that does not.
-__device__ void build_runs(RunLds& R, const BinArgs& a, int cat, int cx, int cy, int cz) {
+__device__ void build_pieces(Pieces& W, const BinArgs& a, int cat, int cx, int cy, int cz) {
     const int lane = lane_id();
-    const int nc = a.g.nc, k = a.g.k;
+    const int nc = a.g.nc, k = a.g.k, K2 = 2 * k + 1;
     const int base = cat * a.g.ncell;
     int total_pieces = 0;
     for (int r0 = 0; r0 < a.nruns; r0 += 64) {
         const int r = r0 + lane;
-        int np = 0;
-        int s0 = 0, e0 = 0, s1 = 0, e1 = 0, w0 = 0, w1 = 0, cb = 0;
+        int s0 = 0, e0 = 0, s1 = 0, e1 = 0, c0 = 0, c1 = 0;
+        float zo0 = 0.f, zo1 = 0.f, sx = 0.f, sy = 0.f;
         bool has_wrap = false, has_in = false;
-        float sxv = 0.f, syv = 0.f, zo0 = 0.f, zo1 = 0.f;
         if (r < a.nruns) {
             const StencilRun st = a.runs[r];
             int qx = cx + st.ox, qy = cy + st.oy;
@@ -125,17 +146,17 @@ __device__ void build_runs(RunLds& R, const BinArgs& a, int cat, int cx, int cy,
             if (qy < 0) { qy += nc; wy = -1; } else if (qy >= nc) { qy -= nc; wy = 1; }
             const int col = base + (qx * nc + qy) * nc;
             const int zlo = cz + st.oz_lo, zhi = cz + st.oz_hi;
-            cb = (st.ox + k) * (2 * k + 1) + (st.oy + k);
-            sxv = (float)(st.ox * a.g.h);
-            syv = (float)(st.oy * a.g.h);
+            const int cbk = ((st.ox + k) * K2 + (st.oy + k)) * K2 + k;
             const int wxy = (wx + 1) | ((wy + 1) << 2);
+            sx = (float)(st.ox * a.g.h);
+            sy = (float)(st.oy * a.g.h);
             if (zlo < 0) {
                 // cells zlo..min(zhi,-1) are nc+zlo..nc+min(zhi,-1); z offset = izf - nc - cz
                 const int za = zlo + nc, zb = min(zhi, -1) + nc;
                 s0 = a.cell_start[col + za];
                 e0 = a.cell_start[col + zb + 1];
                 zo0 = (float)(-nc - cz);
-                w0 = wxy | (0 << 4);
+                c0 = cbk | ((wxy | (0 << 4)) << 16);
                 has_wrap = true;
             } else if (zhi > nc - 1) {
                 // cells max(zlo,nc)..zhi are those minus nc; z offset = izf + nc - cz
@@ -143,7 +164,7 @@ __device__ void build_runs(RunLds& R, const BinArgs& a, int cat, int cx, int cy,
                 s0 = a.cell_start[col + za];
                 e0 = a.cell_start[col + zb + 1];
                 zo0 = (float)(nc - cz);
-                w0 = wxy | (2 << 4);
+                c0 = cbk | ((wxy | (2 << 4)) << 16);
                 has_wrap = true;
             }
             const int lo_in = max(zlo, 0), hi_in = min(zhi, nc - 1);
@@ -151,11 +172,11 @@ __device__ void build_runs(RunLds& R, const BinArgs& a, int cat, int cx, int cy,
                 s1 = a.cell_start[col + lo_in];
                 e1 = a.cell_start[col + hi_in + 1];
                 zo1 = (float)(-cz);
-                w1 = wxy | (1 << 4);
+                c1 = cbk | ((wxy | (1 << 4)) << 16);
                 has_in = true;
             }
-            np = (int)has_wrap + (int)has_in;
         }
+        const int np = (int)has_wrap + (int)has_in;
         int incl = np;
         for (int off = 1; off < 64; off <<= 1) {
             const int t = __shfl_up(incl, off, 64);
@@ -163,243 +184,324 @@ __device__ void build_runs(RunLds& R, const BinArgs& a, int cat, int cx, int cy,
         }
         int q = total_pieces + incl - np;
         if (has_wrap) {
-            R.start[q] = s0;
-            R.pref[q] = e0 - s0;
-            R.sx[q] = sxv; R.sy[q] = syv; R.zo[q] = zo0;
-            R.code[q] = cb;
-            R.wrap[q] = w0;
+            W.rec[q] = make_float4(__int_as_float(s0), sx, sy, zo0);
+            W.pref[q] = e0 - s0;
+            W.code[q] = c0;
             ++q;
         }
         if (has_in) {
-            R.start[q] = s1;
-            R.pref[q] = e1 - s1;
-            R.sx[q] = sxv; R.sy[q] = syv; R.zo[q] = zo1;
-            R.code[q] = cb;
-            R.wrap[q] = w1;
+            W.rec[q] = make_float4(__int_as_float(s1), sx, sy, zo1);
+            W.pref[q] = e1 - s1;
+            W.code[q] = c1;
         }
         total_pieces += __shfl(incl, 63, 64);
     }
     wave_sync();
-    // exclusive prefix of the piece lengths (held in pref) -> pref
+    // exclusive prefix of the piece lengths (held in pref) -> pref, and the
+    // point offset off = start - pref into rec.x
     int carry = 0;
     for (int q0 = 0; q0 < total_pieces; q0 += 64) {
         const int q = q0 + lane;
-        const int len = q < total_pieces ? R.pref[q] : 0;
+        const int len = q < total_pieces ? W.pref[q] : 0;
         int incl = len;
         for (int off = 1; off < 64; off <<= 1) {
             const int t = __shfl_up(incl, off, 64);
             if (lane >= off) incl += t;
         }
         wave_sync();
-        if (q < total_pieces) R.pref[q] = carry + incl - len;
+        if (q < total_pieces) {
+            const int pr = carry + incl - len;
+            W.pref[q] = pr;
+            W.rec[q].x = __int_as_float(__float_as_int(W.rec[q].x) - pr);
+        }
         carry += __shfl(incl, 63, 64);
         wave_sync();
     }
     if (lane == 0) {
-        R.pref[total_pieces] = carry;
-        R.n = total_pieces;
+        W.pref[total_pieces] = carry;
+        *W.n = total_pieces;
     }
     wave_sync();
 }
 
-// Classifies candidate g of the flattened range: returns its bin (or -1) and
-// its list entry. r is the piece holding g.
-template <bool FP64>
-__device__ __forceinline__ int classify(const BinLds& L, const BinArgs& a, int64_t p,
-                                        const float4& P32, const double4& P64, int r, int g,
-                                        int64_t cstart, int k, uint32_t& entry) {
-    const int64_t j = L.r.start[r] + (g - L.r.pref[r]);
-    const float4 q = a.pf[j];
-    const int oz = (int)(q.w + L.r.zo[r]);
-    const int wb = L.r.wrap[r];
-    int b = -1;
-    if (j != p) {
-        if (FP64) {
-            b = exact_bin(P64, a.pd[j], wb, a);
-        } else {
-            float dx, dy, dz;
-            if (a.g.single) {
-                dx = q.x - P32.x;
-                dy = q.y - P32.y;
-                dz = q.z - P32.z;
-                dx -= a.g.boxf * rintf(dx / a.g.boxf);
-                dy -= a.g.boxf * rintf(dy / a.g.boxf);
-                dz -= a.g.boxf * rintf(dz / a.g.boxf);
-            } else {
-                dx = (q.x - P32.x) + L.r.sx[r];
-                dy = (q.y - P32.y) + L.r.sy[r];
-                dz = fmaf((float)oz, a.g.hf, q.z - P32.z);
-            }
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= a.e2f[0] - a.guard[0] && r2 < a.e2f[a.nb] + a.guard[a.nb]) {
-                int bb = a.lut[min(kLut - 1, max(0, (int)((r2 - a.e2f[0]) * a.lut_scale)))];
-                while (bb + 1 < a.nb && r2 >= a.e2f[bb + 1]) ++bb;
-                while (bb > 0 && r2 < a.e2f[bb]) --bb;
-                const bool near = fabsf(r2 - a.e2f[bb]) < a.guard[bb] ||
-                                  fabsf(a.e2f[bb + 1] - r2) < a.guard[bb + 1] ||
-                                  r2 < a.e2f[0] || r2 >= a.e2f[a.nb];
-                b = near ? exact_bin(P64, a.pd[j], wb, a) : bb;
-            }
-        }
+// Last piece r with pref[r] <= g (pieces may be empty), branch-free.
+__device__ __forceinline__ int find_piece(const int* pref, int np, int g) {
+    int r = 0;
+#pragma unroll
+    for (int step = 128; step > 0; step >>= 1) {
+        const int c = r + step;
+        r = (c < np && pref[c] <= g) ? c : r;
     }
-    if (b >= 0) {
-        const int code = a.g.single ? 0 : L.r.code[r] * (2 * k + 1) + (oz + k);
-        entry = (uint32_t)(j - cstart) | ((uint32_t)code << (32 - a.g.code_bits));
-    }
-    return b;
+    return r;
 }
 
-// One scan over the candidates. Hits with bin in [blo, bhi) are appended to
-// the LDS buffer (up to kHB); with COUNT the per-bin totals of all hits are
-// accumulated in L.cnt.
-template <bool FP64, bool COUNT>
-__device__ int scan_candidates(BinLds& L, const BinArgs& a, int64_t p, const float4& P32,
-                               const double4& P64, int blo, int bhi, int64_t cstart, int k) {
-    const int lane = lane_id();
-    const int total = L.r.pref[L.r.n];
-    int tot = 0;
-    int rcur = 0;
-    for (int t = 0; t < total; t += 64) {
-        while (L.r.pref[rcur + 1] <= t) ++rcur;
-        const int g = t + lane;
-        int b = -1;
-        uint32_t entry = 0;
-        if (g < total) {
-            int r = rcur;
-            while (L.r.pref[r + 1] <= g) ++r;
-            b = classify<FP64>(L, a, p, P32, P64, r, g, cstart, k, entry);
-            if (COUNT && b >= 0) atomicAdd(&L.cnt[b], 1);
-        }
-        const bool keep = b >= blo && b < bhi;
-        const uint64_t m = __ballot(keep);
-        if (keep) {
-            const int pos = tot + lanes_below(m);
-            if (pos < kHB) {
-                L.buf[pos] = entry;
-                L.bbuf[pos] = (unsigned char)b;
-            }
-        }
-        tot += __popcll(m);
-    }
-    wave_sync();
-    return tot;
+// Wrap signs (+1, 2 bits per axis) of stencil offset `code` seen from cell
+// (cx, cy, cz): -1 where the neighbour cell index wrapped below 0, +1 above nc-1.
+__device__ inline int wrap_bits_of(int code, int cx, int cy, int cz, int k, int nc) {
+    const int K2 = 2 * k + 1;
+    const int ox = code / (K2 * K2) - k, oy = (code / K2) % K2 - k, oz = code % K2 - k;
+    auto w = [&](int c, int o) { const int q = c + o; return q < 0 ? 0 : (q >= nc ? 2 : 1); };
+    return w(cx, ox) | (w(cy, oy) << 2) | (w(cz, oz) << 4);
 }
 
-// Writes the LDS hits (bins [blo,bhi)) to global memory, each bin's hits in
-// candidate order at base + pre[b].
-__device__ void write_hits(BinLds& L, const BinArgs& a, int tot, uint32_t base_off, int blo,
-                           int bhi) {
-    const int lane = lane_id();
-    int runv = 0;  // lane bb holds the hits of bin bb written so far
-    for (int e0 = 0; e0 < tot; e0 += 64) {
-        const int e = e0 + lane;
-        const int b = e < tot ? (int)L.bbuf[e] : -1;
-        const uint32_t v = e < tot ? L.buf[e] : 0u;
-        int rank = 0;
-        for (int bb = blo; bb < bhi; ++bb) {
-            const uint64_t m = __ballot(b == bb);
-            if (m == 0) continue;
-            const int basebb = __shfl(runv, bb, 64);
-            if (b == bb) rank = basebb + lanes_below(m);
-            if (lane == bb) runv += __popcll(m);
-        }
-        if (b >= 0) a.list[base_off + (uint32_t)L.pre[b] + (uint32_t)rank] = v;
-    }
-    wave_sync();
+// Exact bin of the pair (primary p, candidate with list entry `entry`) for a
+// pair inside an FP32 guard band. Out of line: it is rare.
+template <bool SINGLE>
+__device__ __noinline__ int exact_pair(const double4* pd, int64_t p, int64_t cstart, uint32_t entry,
+                                       uint32_t mask, int cshift, int cx, int cy, int cz, int k, int nc,
+                                       double box, int nb, const double* e2) {
+    const int64_t j = cstart + (int64_t)(entry & mask);
+    const int wb = SINGLE ? 0 : wrap_bits_of((int)(entry >> cshift), cx, cy, cz, k, nc);
+    return exact_bin_t<SINGLE>(pd[p], pd[j], wb, box, nb, e2);
 }
 
-template <bool FP64>
-__global__ void __launch_bounds__(256) k_pair_bin(BinArgs a) {
+constexpr int kNW = 4;                     // wavefronts per workgroup
+constexpr int kGM = kItemPrims / kNW;      // primaries per wavefront
+constexpr int kTile = 512;                 // candidates per LDS tile
+constexpr int kUT = kTile / 64;            // tile candidates per lane
+constexpr int kStage = kTile / (64 * kNW); // candidates each thread stages per tile
+constexpr uint32_t kNoBase = 0xffffffffu;
+static_assert(kGM * kNW == kItemPrims, "item size");
+
+// A candidate being staged: the point (cell-relative FP32), its piece's shift
+// and its index, held in registers while the previous tile is tested.
+struct Staged {
+    float4 q;
+    float sx, sy, zo;
+    int code;
+    uint32_t j;
+    bool ok;
+};
+
+template <bool SINGLE>
+__device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, int total, int g,
+                                           const float4* pf) {
+    st.ok = g < total;
+    if (st.ok) {
+        const int r = find_piece(S.pref, np, g);
+        const float4 rc = S.rec[r];
+        st.j = (uint32_t)(g + __float_as_int(rc.x));
+        st.sx = rc.y;
+        st.sy = rc.z;
+        st.zo = rc.w;
+        st.code = S.code[r] & 0xffff;
+        st.q = pf[st.j];
+    }
+}
+
+// Writes a staged candidate in the home cell's frame: (x, y, z, list entry),
+// entry = catalogue-relative index | stencil code << cshift.
+template <bool SINGLE>
+__device__ __forceinline__ void stage_store(const Staged& st, float4* dst, uint32_t cst, int cshift, float hf) {
+    if (!st.ok) return;
+    float4 v;
+    if constexpr (SINGLE) {
+        v = make_float4(st.q.x, st.q.y, st.q.z, __uint_as_float(st.j - cst));
+    } else {
+        const int oz = (int)(st.q.w + st.zo);
+        v.x = st.q.x + st.sx;
+        v.y = st.q.y + st.sy;
+        v.z = fmaf((float)oz, hf, st.q.z);
+        v.w = __uint_as_float((st.j - cst) | ((uint32_t)(st.code + oz) << cshift));
+    }
+    *dst = v;
+}
+
+// Binning of the pairs of a work item (up to kItemPrims primaries of one home
+// cell) in two sweeps over the cell's candidates. Sweep 0 counts the hits of
+// every (primary, bin) with LDS atomics; the counts give each primary one
+// allocation in the list, laid out bin by bin. Sweep 1 repeats the same tests
+// and writes each hit to its final place, so no hit is buffered. Candidates
+// are staged in LDS once per tile for the whole workgroup, in the home cell's
+// frame, and every wavefront tests them against its primaries (kGM at most),
+// double-buffered so that the loads of the next tile overlap the tests.
+template <bool SINGLE, bool UNIFORM>
+__global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     extern __shared__ unsigned char smem[];
-    BinLds& L = reinterpret_cast<BinLds*>(smem)[threadIdx.x >> 6];
+    BinTables& T = *reinterpret_cast<BinTables*>(smem);
+    for (int i = threadIdx.x; i <= a.nb; i += blockDim.x) {
+        T.e2[i] = a.e2[i];
+        T.e2f[i] = a.e2f[i];
+        T.guard[i] = a.guard[i];
+    }
+    size_t off = (sizeof(BinTables) + 15) / 16 * 16;
+    float4* tiles = reinterpret_cast<float4*>(smem + off);
+    off += sizeof(float4) * 2 * kTile;
+    Pieces S = pieces_view(smem + off, a.npmax);
+    off += pieces_lds_bytes(a.npmax);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
-    const int64_t nprim = a.p_end - a.p_begin;
-    const int64_t nblk = (nprim + 3) / 4;
-    const int64_t blk = xcd_block(blockIdx.x, (int64_t)gridDim.x);
-    if (blk >= nblk) return;
-    const int64_t p = a.p_begin + blk * 4 + (threadIdx.x >> 6);
-    if (p >= a.p_end) return;
-    const int64_t pl = p - a.p_begin;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(smem + off) + wave * (kGM * kMaxBins);
 
-    const float4 P32 = a.pf[p];
-    const double4 P64 = a.pd[p];
-    const int cat = a.catid[p];
+    const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
+    if (item >= a.item_hi) return;
+    const int gc = a.item_cell[item];
+    const int64_t first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
+    const int64_t cs = max(first, a.p_begin);
+    const int64_t ce = min(min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]), a.p_end);
+    if (cs >= ce) return;
+    const int cat = gc / a.g.ncell;
+    const int loc = gc - cat * a.g.ncell;
+    const int cz = loc % a.g.nc, cy = (loc / a.g.nc) % a.g.nc, cx = loc / (a.g.nc * a.g.nc);
     const int64_t cstart = a.pt_off[cat];
-    int cx = 0, cy = 0, cz = 0;
-    if (!a.g.single) {
-        cz = (int)P32.w;
-        // x and y cells from the FP64 position, with the same rule as the grid build
-        cx = min(a.g.nc - 1, max(0, (int)(P64.x * a.g.inv_h)));
-        cy = min(a.g.nc - 1, max(0, (int)(P64.y * a.g.inv_h)));
-    }
-    if (lane < kMaxBins) L.cnt[lane] = 0;
-    wave_sync();
-    build_runs(L.r, a, cat, cx, cy, cz);
+    const uint32_t cst = (uint32_t)cstart;
+    const int cshift = 32 - a.g.code_bits;
+    const uint32_t mask = a.g.idx_mask;
+    if (wave == 0) build_pieces(S, a, cat, SINGLE ? 0 : cx, SINGLE ? 0 : cy, SINGLE ? 0 : cz);
+    __syncthreads();
+    const int np = *S.n;
+    const int total = S.pref[np];
 
-    const int k = a.g.k;
-    const int tot = scan_candidates<FP64, true>(L, a, p, P32, P64, 0, a.nb, cstart, k);
-    // per-bin counts and offsets
-    const int c = lane < a.nb ? L.cnt[lane] : 0;
-    int incl = c;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += t;
-    }
-    const int total_hits = __shfl(incl, 63, 64);
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(a.cursor, (unsigned long long)total_hits);
-    base = __shfl(base, 0, 64);
-    if (base + (unsigned long long)total_hits > a.capacity) {
-        if (lane == 0) atomicOr(a.overflow, 1);
-        if (lane < a.nb) {
-            a.cnt[pl * a.nb + lane] = 0;
-            a.boff[pl * a.nb + lane] = 0;
+    // this wavefront's primaries: cs + wave + kNW g, g < ng
+    const int rem = (int)(ce - cs);
+    const int ng = rem > wave ? (rem - wave + kNW - 1) / kNW : 0;
+    float px[kGM], py[kGM], pz[kGM];
+#pragma unroll
+    for (int g = 0; g < kGM; ++g) {
+        px[g] = py[g] = pz[g] = 0.f;
+        if (g < ng) {
+            const float4 P = a.pf[cs + wave + kNW * g];
+            px[g] = P.x;
+            py[g] = P.y;
+            pz[g] = P.z;
         }
-        return;
     }
-    if (lane < a.nb) {
-        L.pre[lane] = incl - c;
-        a.cnt[pl * a.nb + lane] = (uint32_t)c;
-        a.boff[pl * a.nb + lane] = (uint32_t)(base + (unsigned long long)(incl - c));
-    }
-    wave_sync();
-    if (tot <= kHB) {
-        write_hits(L, a, tot, (uint32_t)base, 0, a.nb);
-        return;
-    }
-    // More hits than the LDS buffer: rescan in passes over runs of bins that
-    // fit. A bin larger than the buffer is streamed to global memory in
-    // candidate order.
-    int blo = 0;
-    while (blo < a.nb) {
-        int bhi = blo, sum = 0;
-        while (bhi < a.nb && sum + L.cnt[bhi] <= kHB) { sum += L.cnt[bhi]; ++bhi; }
-        if (bhi > blo) {
-            const int got = scan_candidates<FP64, false>(L, a, p, P32, P64, blo, bhi, cstart, k);
-            write_hits(L, a, got, (uint32_t)base, blo, bhi);
-            blo = bhi;
-            continue;
+    for (int i = lane; i < kGM * kMaxBins; i += 64) cnt[i] = 0u;
+    uint32_t base[kGM];
+#pragma unroll
+    for (int g = 0; g < kGM; ++g) base[g] = kNoBase;
+    const float ne0 = -a.e0f * a.inv_dr;
+    const float lo2 = T.e2f[0] - T.guard[0];
+    const float hi2 = T.e2f[a.nb] + T.guard[a.nb];
+    const unsigned nbu = (unsigned)a.nb;
+
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        Staged st[kStage];
+        // prologue: tile 0
+#pragma unroll
+        for (int s = 0; s < kStage; ++s) {
+            const int i = s * 64 * kNW + threadIdx.x;
+            stage_load<SINGLE>(st[s], S, np, total, i, a.pf);
+            stage_store<SINGLE>(st[s], tiles + i, cst, cshift, a.g.hf);
         }
-        const int b1 = blo;
-        const int total = L.r.pref[L.r.n];
-        int written = 0;
-        int rcur = 0;
-        for (int t = 0; t < total; t += 64) {
-            while (L.r.pref[rcur + 1] <= t) ++rcur;
-            const int g = t + lane;
-            int b = -1;
-            uint32_t entry = 0;
-            if (g < total) {
-                int r = rcur;
-                while (L.r.pref[r + 1] <= g) ++r;
-                b = classify<FP64>(L, a, p, P32, P64, r, g, cstart, k, entry);
+        __syncthreads();
+        int buf = 0;
+        for (int t = 0; t < total; t += kTile) {
+            const float4* cur = tiles + buf * kTile;
+            const bool more = t + kTile < total;
+            if (more) {
+#pragma unroll
+                for (int s = 0; s < kStage; ++s)
+                    stage_load<SINGLE>(st[s], S, np, total, t + kTile + s * 64 * kNW + (int)threadIdx.x, a.pf);
             }
-            const bool keep = b == b1;
-            const uint64_t m = __ballot(keep);
-            if (keep) a.list[(uint32_t)base + (uint32_t)L.pre[b1] + (uint32_t)(written + lanes_below(m))] = entry;
-            written += __popcll(m);
+            const int nt = min(kTile, total - t);
+#pragma unroll 2
+            for (int u = 0; u < kUT; ++u) {
+                const int i = u * 64 + lane;
+                const float4 c = cur[i];
+                const bool valid = i < nt;
+                const uint32_t entry = __float_as_uint(c.w);
+#pragma unroll
+                for (int g = 0; g < kGM; ++g) {
+                    if (g >= ng) break;
+                    float dx = c.x - px[g], dy = c.y - py[g], dz = c.z - pz[g];
+                    if constexpr (SINGLE) {
+                        dx -= a.g.boxf * rintf(dx * a.inv_boxf);
+                        dy -= a.g.boxf * rintf(dy * a.inv_boxf);
+                        dz -= a.g.boxf * rintf(dz * a.inv_boxf);
+                    }
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    int bb;
+                    bool near;
+                    if constexpr (UNIFORM) {
+                        const float uu = fmaf(__builtin_amdgcn_sqrtf(r2), a.inv_dr, ne0);
+                        const float fl = floorf(uu);
+                        bb = (int)fl;
+                        const float fr = uu - fl;
+                        // guard bands of the edges e_0 .. e_nb: bb in [-1, nb]
+                        near = (fr < a.delta || fr > 1.0f - a.delta) && (unsigned)(bb + 1) <= nbu + 1u;
+                    } else {
+                        bb = -1;
+                        near = false;
+                        if (r2 >= lo2 && r2 < hi2) {
+                            for (int e = 0; e <= a.nb; ++e) {
+                                bb += r2 >= T.e2f[e];
+                                near |= fabsf(r2 - T.e2f[e]) < T.guard[e];
+                            }
+                        }
+                    }
+                    int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
+                    if (valid && near) {
+                        b = exact_pair<SINGLE>(a.pd, cs + wave + kNW * g, cstart, entry, mask, cshift, cx, cy,
+                                               cz, a.g.k, a.g.nc, a.g.box, a.nb, T.e2);
+                    }
+                    if (b >= 0) {
+                        if (sweep == 0) {
+                            atomicAdd(&cnt[g * kMaxBins + b], 1u);
+                        } else if (base[g] != kNoBase) {
+                            // the LDS unit serves the lanes of one atomic in a
+                            // fixed order, so the lists are the same on every run
+                            const uint32_t pos = atomicAdd(&cnt[g * kMaxBins + b], 1u);
+                            a.list[base[g] + pos] = entry;
+                        }
+                    }
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int s = 0; s < kStage; ++s)
+                    stage_store<SINGLE>(st[s], tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, cst,
+                                        cshift, a.g.hf);
+            }
+            __syncthreads();
+            buf ^= 1;
         }
-        blo = b1 + 1;
+        if (sweep == 1) break;
+
+        // counts -> one allocation per wavefront; cnt becomes the offset of each
+        // bin inside its primary's allocation
+        wave_sync();
+        uint32_t tot[kGM], cl[kGM], ex[kGM];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int g = 0; g < kGM; ++g) {
+            tot[g] = cl[g] = ex[g] = 0;
+            if (g >= ng) continue;
+            const int c = lane < a.nb ? (int)cnt[g * kMaxBins + lane] : 0;
+            int incl = c;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            tot[g] = (uint32_t)__shfl(incl, 63, 64);
+            cl[g] = (uint32_t)c;
+            ex[g] = (uint32_t)(incl - c);
+            if (lane < a.nb) cnt[g * kMaxBins + lane] = ex[g];
+            sum += tot[g];
+        }
+        if (ng > 0) {
+            const int64_t pl0 = cs + wave - a.p_begin;
+            const int slot = (int)(pl0 % kSlots);
+            const unsigned long long region = a.capacity / kSlots;
+            unsigned long long b0 = 0;
+            if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
+            b0 = __shfl(b0, 0, 64);
+            const bool ok = b0 + sum <= region;
+            if (!ok && lane == 0) atomicOr(a.overflow, 1);
+            uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
+#pragma unroll
+            for (int g = 0; g < kGM; ++g) {
+                if (g >= ng) continue;
+                const int64_t pl = cs + wave + kNW * g - a.p_begin;
+                if (lane < a.nb) {
+                    a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
+                    a.boff[pl * a.nb + lane] = ok ? run + ex[g] : 0u;
+                }
+                if (ok) base[g] = run;
+                run += tot[g];
+            }
+        }
+        wave_sync();
     }
 }
 
@@ -535,20 +637,36 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
     }
     const uint32_t mask = a.g.idx_mask;
     const int cshift = 32 - a.g.code_bits;
+    // Software pipeline: the list entry of hit t+2 and the point data of hit
+    // t+1 are in flight while hit t is accumulated.
+    uint32_t e0 = n > 0 ? a.list[off] : 0u;
+    uint32_t e1 = n > 1 ? a.list[off + 1] : 0u;
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float w0f = 0.f;
+    double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (n > 0) {
+        const int64_t j = cstart + (int64_t)(e0 & mask);
+        if constexpr (sizeof(T) == 4) { q0 = a.pf[j]; w0f = a.pw[j]; } else { d0 = a.pd[j]; }
+    }
     for (uint32_t t = 0; t < n; ++t) {
-        const uint32_t e = a.list[off + t];
-        const int64_t j = cstart + (int64_t)(e & mask);
+        const uint32_t e2 = t + 2 < n ? a.list[off + t + 2] : 0u;
+        float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float w1f = 0.f;
+        double4 d1 = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (t + 1 < n) {
+            const int64_t j = cstart + (int64_t)(e1 & mask);
+            if constexpr (sizeof(T) == 4) { q1 = a.pf[j]; w1f = a.pw[j]; } else { d1 = a.pd[j]; }
+        }
         T x, y, z, w;
         if constexpr (sizeof(T) == 4) {
-            const float4 q = a.pf[j];
-            w = a.pw[j];
-            float dx = q.x - P32.x, dy = q.y - P32.y, dz = q.z - P32.z;
+            w = w0f;
+            float dx = q0.x - P32.x, dy = q0.y - P32.y, dz = q0.z - P32.z;
             if (a.g.single) {
                 dx -= a.g.boxf * rintf(dx / a.g.boxf);
                 dy -= a.g.boxf * rintf(dy / a.g.boxf);
                 dz -= a.g.boxf * rintf(dz / a.g.boxf);
             } else {
-                const int code = (int)(e >> cshift);
+                const int code = (int)(e0 >> cshift);
                 dx += sh[3 * code];
                 dy += sh[3 * code + 1];
                 dz += sh[3 * code + 2];
@@ -557,9 +675,8 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
             const float inv = __builtin_amdgcn_rsqf(r2);
             x = dx * inv; y = dy * inv; z = dz * inv;
         } else {
-            const double4 q = a.pd[j];
-            w = q.w;
-            double dx = q.x - P64.x, dy = q.y - P64.y, dz = q.z - P64.z;
+            w = d0.w;
+            double dx = d0.x - P64.x, dy = d0.y - P64.y, dz = d0.z - P64.z;
             const double L = a.g.box, hL = 0.5 * a.g.box;
             dx = dx > hL ? dx - L : (dx < -hL ? dx + L : dx);
             dy = dy > hL ? dy - L : (dy < -hL ? dy + L : dy);
@@ -571,6 +688,11 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
             x = dx * inv; y = dy * inv; z = dz * inv;
         }
         add_hit<T, LMAX, G>(acc, x, y, z, w);
+        e0 = e1;
+        e1 = e2;
+        q0 = q1;
+        w0f = w1f;
+        d0 = d1;
     }
     if (!active) return;
     T* A = reinterpret_cast<T*>(a.A);
@@ -619,17 +741,30 @@ hipError_t launch_alm_lmax(const AlmArgs& a, int fp64, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
-    const int64_t nprim = a.p_end - a.p_begin;
-    if (nprim <= 0) return hipSuccess;
-    int64_t nblk = (nprim + 3) / 4;
-    nblk = (nblk + 7) / 8 * 8;
-    const size_t lds = 4 * sizeof(BinLds);
-    if (a.fp64)
-        hipLaunchKernelGGL(k_pair_bin<true>, dim3((unsigned)nblk), dim3(256), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_pair_bin<false>, dim3((unsigned)nblk), dim3(256), lds, s, a);
+template <bool SINGLE, bool UNIFORM>
+hipError_t launch_bin_variant(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void*)k_pair_bin<SINGLE, UNIFORM>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_pair_bin<SINGLE, UNIFORM>), dim3((unsigned)nblk), dim3(64 * kNW), lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
+    const int64_t nitems = a.item_hi - a.item_lo;
+    if (a.p_end <= a.p_begin || nitems <= 0) return hipSuccess;
+    // a multiple of 8 blocks, so that the XCD remap is a permutation
+    const int64_t nblk = (nitems + 7) / 8 * 8;
+    const size_t lds = pair_bin_lds_bytes(a.npmax);
+    if (a.g.single) {
+        return a.uniform ? launch_bin_variant<true, true>(a, s, nblk, lds)
+                         : launch_bin_variant<true, false>(a, s, nblk, lds);
+    }
+    return a.uniform ? launch_bin_variant<false, true>(a, s, nblk, lds)
+                     : launch_bin_variant<false, false>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {
@@ -652,6 +787,9 @@ hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {
     }
 }
 
-size_t pair_bin_lds_bytes() { return 4 * sizeof(BinLds); }
+size_t pair_bin_lds_bytes(int npmax) {
+    return (sizeof(BinTables) + 15) / 16 * 16 + sizeof(float4) * 2 * kTile + pieces_lds_bytes(npmax) +
+           sizeof(uint32_t) * kNW * kGM * kMaxBins;
+}
 
 }  // namespace tpcf
