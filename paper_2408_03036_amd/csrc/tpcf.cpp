@@ -704,6 +704,7 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     c.goff = P<int64_t>(h->d_goff);
     c.mode = h->mode;
     c.unit_weights = h->unit_w ? 1 : 0;
+    c.pw = P<float>(h->d_pw);
     HIPCHK(launch_contract(c, h->stream));
     SelfArgs s{};
     s.A = h->d_A.p;

@@ -240,6 +240,230 @@ __global__ void __launch_bounds__(256) k_contract(ContractArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- split-BF16 contraction
+// Eight wavefronts per workgroup, up to two 32x32 output tiles each. Per step
+// (KS primaries of one part), every thread stages 8 consecutive primaries of
+// one column: two vector loads, packed round-to-nearest BF16 conversion of the
+// pieces, one 16-byte LDS store per plane. Two LDS buffers: the loads of the
+// next step are in flight while the MFMAs of the current one run.
+constexpr int kBfWaves = 8;
+constexpr int kBfTPW = 2;
+constexpr int kBfIPT = 2;  // staged 8-element groups per thread and step
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t cvt_pk_bf16(float a, float b) {
+    bf16x2_t v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// Splits 8 floats into NPC BF16 pieces, piece q as 4 packed dwords.
+template <int NPC>
+__device__ inline void split8(float (&x)[8], uint4 (&out)[NPC]) {
+#pragma unroll
+    for (int q = 0; q < NPC; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w[j] = cvt_pk_bf16(x[2 * j], x[2 * j + 1]);
+            if (q + 1 < NPC) {
+                x[2 * j] -= __uint_as_float(w[j] << 16);
+                x[2 * j + 1] -= __uint_as_float(w[j] & 0xffff0000u);
+            }
+        }
+        out[q] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+struct BfStage {
+    float x[kBfIPT][8];
+    float w[kBfIPT][8];
+};
+
+template <int NPC>
+__global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a, int KS, int nbuf) {
+    constexpr int TS = 32;
+    extern __shared__ unsigned char smem[];
+    const int s = blockIdx.x;
+    const int m = blockIdx.y;
+    const int lmax = a.lmax, nb = a.nb;
+    const int nl = lmax - m + 1;
+    const int K = nb * nl;
+    const int nt = (K + TS - 1) / TS;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int t0 = blockIdx.z * kBfWaves * kBfTPW;
+    if (t0 >= ntiles) return;
+    const int parts = m == 0 ? 1 : 2;
+    const int NV = n_values(lmax);
+    const int voff = value_offset(lmax, m);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
+    const int ncol = nt * TS;
+    const int KSP = KS + 8;
+    const bool weighted = !a.unit_weights;
+    const int nplanes = weighted ? 2 * NPC : NPC;
+    const int plane = ncol * KSP;                 // elements per plane
+    const int bufsz = nplanes * plane;            // elements per buffer
+    uint16_t* lds = reinterpret_cast<uint16_t*>(smem);
+    const float* A = reinterpret_cast<const float*>(a.A);
+
+    int ti[kBfTPW], tj[kBfTPW];
+    bool tv[kBfTPW];
+#pragma unroll
+    for (int q = 0; q < kBfTPW; ++q) {
+        const int t = t0 + wave + kBfWaves * q;
+        tv[q] = t < ntiles;
+        tile_of(tv[q] ? t : 0, nt, ti[q], tj[q]);
+    }
+    f32x16 acc32[kBfTPW];
+    double accd[kBfTPW][16];
+#pragma unroll
+    for (int q = 0; q < kBfTPW; ++q) {
+        acc32[q] = (f32x16)0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accd[q][r] = 0.0;
+    }
+
+    const int groups = KS / 8;
+    const int nitems = ncol * groups;
+    const int nkst = (int)((pb - pa + KS - 1) / KS);
+    const int nsteps = nkst * parts;
+
+    // loads of step st into registers
+    auto load = [&](int st, BfStage& R) {
+        const int part = st % parts;
+        const int64_t p0 = pa + (int64_t)(st / parts) * KS;
+        const int kv = (int)min((int64_t)KS, pb - p0);
+#pragma unroll
+        for (int u = 0; u < kBfIPT; ++u) {
+            const int it = threadIdx.x + u * 64 * kBfWaves;
+            const int c = it / groups, k8 = (it - c * groups) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                R.x[u][e] = 0.f;
+                R.w[u][e] = 0.f;
+            }
+            if (it >= nitems || c >= K || k8 >= kv) continue;
+            const int b = c / nl, lp = c - b * nl;
+            const int64_t row = (int64_t)b * NV + voff + part * nl + lp;
+            const float* src = A + row * a.ldA + p0 + k8;
+            const float* wsrc = a.pw + a.p_begin + p0 + k8;
+            if (k8 + 8 <= kv) {
+                float4 v0, v1;
+                __builtin_memcpy(&v0, src, 16);
+                __builtin_memcpy(&v1, src + 4, 16);
+                R.x[u][0] = v0.x; R.x[u][1] = v0.y; R.x[u][2] = v0.z; R.x[u][3] = v0.w;
+                R.x[u][4] = v1.x; R.x[u][5] = v1.y; R.x[u][6] = v1.z; R.x[u][7] = v1.w;
+                if (weighted) {
+                    __builtin_memcpy(&v0, wsrc, 16);
+                    __builtin_memcpy(&v1, wsrc + 4, 16);
+                    R.w[u][0] = v0.x; R.w[u][1] = v0.y; R.w[u][2] = v0.z; R.w[u][3] = v0.w;
+                    R.w[u][4] = v1.x; R.w[u][5] = v1.y; R.w[u][6] = v1.z; R.w[u][7] = v1.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (k8 + e < kv) {
+                        R.x[u][e] = src[e];
+                        if (weighted) R.w[u][e] = wsrc[e];
+                    }
+                }
+            }
+        }
+    };
+    // converts the registers of a step into BF16 planes of buffer `buf`
+    auto store = [&](int buf, BfStage& R) {
+        uint16_t* base = lds + buf * bufsz;
+#pragma unroll
+        for (int u = 0; u < kBfIPT; ++u) {
+            const int it = threadIdx.x + u * 64 * kBfWaves;
+            if (it >= nitems) continue;
+            const int c = it / groups, k8 = (it - c * groups) * 8;
+            const int off = c * KSP + k8;
+            float y[8];
+            if (weighted) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) y[e] = R.x[u][e] * R.w[u][e];
+            }
+            uint4 pc[NPC];
+            split8<NPC>(R.x[u], pc);
+#pragma unroll
+            for (int q = 0; q < NPC; ++q) *reinterpret_cast<uint4*>(base + q * plane + off) = pc[q];
+            if (weighted) {
+                split8<NPC>(y, pc);
+#pragma unroll
+                for (int q = 0; q < NPC; ++q) *reinterpret_cast<uint4*>(base + (NPC + q) * plane + off) = pc[q];
+            }
+        }
+    };
+
+    BfStage R;
+    load(0, R);
+    store(0, R);
+    __syncthreads();
+    const int i = lane & 31, kg = lane >> 5;
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = nbuf == 2 ? (st & 1) : 0;
+        const bool more = st + 1 < nsteps;
+        if (more && nbuf == 2) load(st + 1, R);
+        const uint16_t* xp = lds + buf * bufsz;
+        const uint16_t* wp = weighted ? xp + NPC * plane : xp;
+        for (int k0 = 0; k0 < KS; k0 += 16) {
+#pragma unroll
+            for (int q = 0; q < kBfTPW; ++q) {
+                if (!tv[q]) continue;
+                const int ra = (ti[q] * TS + i) * KSP + k0 + 8 * kg;
+                const int rb = (tj[q] * TS + i) * KSP + k0 + 8 * kg;
+                bf16x8 ap[NPC], bp[NPC];
+#pragma unroll
+                for (int u = 0; u < NPC; ++u) {
+                    ap[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wp + u * plane + ra));
+                    bp[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(xp + u * plane + rb));
+                }
+                // products of pieces u, v with u + v <= NPC - 1
+#pragma unroll
+                for (int u = 0; u < NPC; ++u)
+#pragma unroll
+                    for (int v2 = 0; v2 < NPC; ++v2)
+                        if (u + v2 <= NPC - 1)
+                            acc32[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[u], bp[v2], acc32[q], 0, 0, 0);
+            }
+        }
+        if (st % parts == parts - 1) {
+            // FP32 accumulation never spans more than one step of KS primaries
+#pragma unroll
+            for (int q = 0; q < kBfTPW; ++q) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) accd[q][r] += (double)acc32[q][r];
+                acc32[q] = (f32x16)0.0f;
+            }
+        }
+        if (more) {
+            if (nbuf == 2) {
+                store(buf ^ 1, R);
+            } else {
+                __syncthreads();
+                load(st + 1, R);
+                store(0, R);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t sg = (int64_t)(a.sub_base + s);
+#pragma unroll
+    for (int q = 0; q < kBfTPW; ++q) {
+        if (!tv[q]) continue;
+        const int j = lane & 31;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int ii = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int ci = ti[q] * TS + ii, cj = tj[q] * TS + j;
+            if (ci < K && cj < K) a.part64[sg * a.gsize + a.goff[m] + (int64_t)ci * K + cj] = accd[q][r];
+        }
+    }
+}
+
 // Degenerate-triangle moments sum_p w_p sum_j w_j^2 R^0_L(z_pj) and pair
 // counts per bin, one workgroup per subchunk, one wavefront per task.
 __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
@@ -396,13 +620,47 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// Step length and buffer count of the split-BF16 contraction: the longest
+// step (64, 32 or 16 primaries) whose staging fits the per-thread registers,
+// double-buffered when both buffers fit in LDS.
+struct BfPlan { int KS, nbuf; size_t lds; };
+BfPlan bf_plan(int npc, int ncol, bool weighted) {
+    const int nplanes = weighted ? 2 * npc : npc;
+    for (int nbuf = 2; nbuf >= 1; --nbuf)
+        for (int KS = 64; KS >= 16; KS /= 2) {
+            if ((size_t)ncol * (KS / 8) > (size_t)64 * kBfWaves * kBfIPT) continue;
+            const size_t lds = (size_t)nbuf * nplanes * ncol * (KS + 8) * sizeof(uint16_t);
+            if (lds <= 160 * 1024) return {KS, nbuf, lds};
+        }
+    return {0, 0, 0};
+}
+
+template <int NPC>
+hipError_t launch_contract_bf16(const ContractArgs& a, hipStream_t s) {
+    const int K0 = a.nb * (a.lmax + 1);
+    const int nt0 = (K0 + 31) / 32;
+    const int ntiles0 = nt0 * (nt0 + 1) / 2;
+    const int ngroups = (ntiles0 + kBfWaves * kBfTPW - 1) / (kBfWaves * kBfTPW);
+    const BfPlan pl = bf_plan(NPC, nt0 * 32, !a.unit_weights);
+    if (pl.KS == 0) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void*)k_contract_bf16<NPC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_contract_bf16<NPC>, dim3(a.nsub, a.lmax + 1, ngroups), dim3(64 * kBfWaves), pl.lds,
+                       s, a, pl.KS, pl.nbuf);
+    return hipGetLastError();
+}
+
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s) {
     if (a.nsub <= 0) return hipSuccess;
     switch (a.mode) {
         case 0: return launch_contract_mode<0>(a, s);
         case 1: return launch_contract_mode<1>(a, s);
-        case 2: return launch_contract_mode<2>(a, s);
-        case 3: return launch_contract_mode<3>(a, s);
+        case 2: return launch_contract_bf16<2>(a, s);
+        case 3: return launch_contract_bf16<3>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -412,8 +670,10 @@ size_t contract_lds_bytes(int mode, int nb, int lmax) {
     switch (mode) {
         case 0: return contract_lds<0>((K0 + 15) / 16 * 16);
         case 1: return contract_lds<1>((K0 + 31) / 32 * 32);
-        case 2: return contract_lds<2>((K0 + 31) / 32 * 32);
-        default: return contract_lds<3>((K0 + 31) / 32 * 32);
+        default: {
+            const BfPlan pl = bf_plan(mode == 2 ? 2 : 3, (K0 + 31) / 32 * 32, true);
+            return pl.KS ? pl.lds : (size_t)-1;
+        }
     }
 }
 

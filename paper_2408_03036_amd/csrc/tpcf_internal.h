@@ -62,7 +62,7 @@ hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const
                             int* perm, int* catid, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
 // Work items of the binning pass: each cell's primaries in blocks of kItemPrims.
-constexpr int kItemPrims = 32;
+constexpr int kItemPrims = 16;
 hipError_t launch_items_count(const int* cell_start, int64_t m, int* nitems, hipStream_t s);
 hipError_t launch_items_fill(const int* item_start, int64_t m, int* item_cell, hipStream_t s);
 hipError_t launch_items_cat(const int* item_start, int ncat, int ncell, int* item_cat, hipStream_t s);
@@ -137,8 +137,9 @@ struct ContractArgs {
     double* part64;          // partial sums (FP64 mode)
     int64_t gsize;           // sum_m K_m^2
     const int64_t* goff;     // [lmax+1] offset of G_m inside a partial
-    int mode;                // 0 fp64, 1 fp32, 2 bf16x3
+    int mode;                // 0 fp64, 1 fp32, 2 bf16x3, 3 bf16x6
     int unit_weights;        // all weights 1: skip the weight multiply
+    const float* pw;         // FP32 weights, sorted order (split-BF16 modes)
 };
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s);
 

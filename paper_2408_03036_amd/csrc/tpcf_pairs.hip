@@ -307,6 +307,109 @@ __device__ __forceinline__ void stage_store(const Staged& st, float4* dst, uint3
     *dst = v;
 }
 
+// State of one work item shared by its two sweeps.
+struct ItemCtx {
+    const Pieces* S;
+    float4* tiles;
+    const BinTables* T;
+    uint32_t* cnt;          // this wavefront's [kGM][kMaxBins] counters / offsets
+    int np, total;
+    int64_t cs, cstart;     // first primary of this wavefront's group, catalogue start
+    uint32_t cst, mask;
+    int cshift, cx, cy, cz, wave, lane, ng;
+};
+
+// One sweep over the item's candidates. SWEEP 0 counts the hits of every
+// (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
+// bin), the offsets having been prepared in cnt.
+template <int SWEEP, bool SINGLE, bool UNIFORM>
+__device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, const float (&px)[kGM],
+                                          const float (&py)[kGM], const float (&pz)[kGM],
+                                          const uint32_t (&base)[kGM]) {
+    const BinTables& T = *c.T;
+    const float ne0 = -a.e0f * a.inv_dr;
+    const float lo2 = T.e2f[0] - T.guard[0];
+    const float hi2 = T.e2f[a.nb] + T.guard[a.nb];
+    const unsigned nbu = (unsigned)a.nb;
+    Staged st[kStage];
+#pragma unroll
+    for (int s = 0; s < kStage; ++s) {
+        const int i = s * 64 * kNW + threadIdx.x;
+        stage_load<SINGLE>(st[s], *c.S, c.np, c.total, i, a.pf);
+        stage_store<SINGLE>(st[s], c.tiles + i, c.cst, c.cshift, a.g.hf);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int t = 0; t < c.total; t += kTile) {
+        const float4* cur = c.tiles + buf * kTile;
+        const bool more = t + kTile < c.total;
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < kStage; ++s)
+                stage_load<SINGLE>(st[s], *c.S, c.np, c.total, t + kTile + s * 64 * kNW + (int)threadIdx.x, a.pf);
+        }
+        const int nt = min(kTile, c.total - t);
+#pragma unroll 2
+        for (int u = 0; u < kUT; ++u) {
+            const int i = u * 64 + c.lane;
+            const float4 q = cur[i];
+            const bool valid = i < nt;
+            const uint32_t entry = __float_as_uint(q.w);
+#pragma unroll
+            for (int g = 0; g < kGM; ++g) {
+                if (g >= c.ng) break;
+                float dx = q.x - px[g], dy = q.y - py[g], dz = q.z - pz[g];
+                if constexpr (SINGLE) {
+                    dx -= a.g.boxf * rintf(dx * a.inv_boxf);
+                    dy -= a.g.boxf * rintf(dy * a.inv_boxf);
+                    dz -= a.g.boxf * rintf(dz * a.inv_boxf);
+                }
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                int bb;
+                bool near;
+                if constexpr (UNIFORM) {
+                    const float uu = fmaf(__builtin_amdgcn_sqrtf(r2), a.inv_dr, ne0);
+                    const float fl = floorf(uu);
+                    bb = (int)fl;
+                    const float fr = uu - fl;
+                    // guard bands of the edges e_0 .. e_nb: bb in [-1, nb]
+                    near = (fr < a.delta || fr > 1.0f - a.delta) && (unsigned)(bb + 1) <= nbu + 1u;
+                } else {
+                    bb = -1;
+                    near = false;
+                    if (r2 >= lo2 && r2 < hi2) {
+                        for (int e = 0; e <= a.nb; ++e) {
+                            bb += r2 >= T.e2f[e];
+                            near |= fabsf(r2 - T.e2f[e]) < T.guard[e];
+                        }
+                    }
+                }
+                int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
+                if (valid && near) {
+                    b = exact_pair<SINGLE>(a.pd, c.cs + c.wave + kNW * g, c.cstart, entry, c.mask, c.cshift,
+                                           c.cx, c.cy, c.cz, a.g.k, a.g.nc, a.g.box, a.nb, T.e2);
+                }
+                if constexpr (SWEEP == 0) {
+                    if (b >= 0) atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
+                } else if (b >= 0 && base[g] != kNoBase) {
+                    // the LDS unit serves the lanes of one atomic in a fixed
+                    // order, so the lists are the same on every run
+                    const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
+                    a.list[base[g] + pos] = entry;
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < kStage; ++s)
+                stage_store<SINGLE>(st[s], c.tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, c.cst,
+                                    c.cshift, a.g.hf);
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
 // Binning of the pairs of a work item (up to kItemPrims primaries of one home
 // cell) in two sweeps over the cell's candidates. Sweep 0 counts the hits of
 // every (primary, bin) with LDS atomics; the counts give each primary one
@@ -329,180 +432,103 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     off += sizeof(float4) * 2 * kTile;
     Pieces S = pieces_view(smem + off, a.npmax);
     off += pieces_lds_bytes(a.npmax);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = lane_id();
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(smem + off) + wave * (kGM * kMaxBins);
+    ItemCtx c;
+    c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    c.lane = lane_id();
+    c.cnt = reinterpret_cast<uint32_t*>(smem + off) + c.wave * (kGM * kMaxBins);
+    c.T = &T;
+    c.S = &S;
+    c.tiles = tiles;
 
     const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
     if (item >= a.item_hi) return;
     const int gc = a.item_cell[item];
     const int64_t first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
-    const int64_t cs = max(first, a.p_begin);
+    c.cs = max(first, a.p_begin);
     const int64_t ce = min(min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]), a.p_end);
-    if (cs >= ce) return;
+    if (c.cs >= ce) return;
     const int cat = gc / a.g.ncell;
     const int loc = gc - cat * a.g.ncell;
-    const int cz = loc % a.g.nc, cy = (loc / a.g.nc) % a.g.nc, cx = loc / (a.g.nc * a.g.nc);
-    const int64_t cstart = a.pt_off[cat];
-    const uint32_t cst = (uint32_t)cstart;
-    const int cshift = 32 - a.g.code_bits;
-    const uint32_t mask = a.g.idx_mask;
-    if (wave == 0) build_pieces(S, a, cat, SINGLE ? 0 : cx, SINGLE ? 0 : cy, SINGLE ? 0 : cz);
+    c.cz = loc % a.g.nc;
+    c.cy = (loc / a.g.nc) % a.g.nc;
+    c.cx = loc / (a.g.nc * a.g.nc);
+    c.cstart = a.pt_off[cat];
+    c.cst = (uint32_t)c.cstart;
+    c.cshift = 32 - a.g.code_bits;
+    c.mask = a.g.idx_mask;
+    if (c.wave == 0) build_pieces(S, a, cat, SINGLE ? 0 : c.cx, SINGLE ? 0 : c.cy, SINGLE ? 0 : c.cz);
     __syncthreads();
-    const int np = *S.n;
-    const int total = S.pref[np];
+    c.np = *S.n;
+    c.total = S.pref[c.np];
 
     // this wavefront's primaries: cs + wave + kNW g, g < ng
-    const int rem = (int)(ce - cs);
-    const int ng = rem > wave ? (rem - wave + kNW - 1) / kNW : 0;
+    const int rem = (int)(ce - c.cs);
+    c.ng = rem > c.wave ? (rem - c.wave + kNW - 1) / kNW : 0;
     float px[kGM], py[kGM], pz[kGM];
+    uint32_t base[kGM];
 #pragma unroll
     for (int g = 0; g < kGM; ++g) {
         px[g] = py[g] = pz[g] = 0.f;
-        if (g < ng) {
-            const float4 P = a.pf[cs + wave + kNW * g];
+        base[g] = kNoBase;
+        if (g < c.ng) {
+            const float4 P = a.pf[c.cs + c.wave + kNW * g];
             px[g] = P.x;
             py[g] = P.y;
             pz[g] = P.z;
         }
     }
-    for (int i = lane; i < kGM * kMaxBins; i += 64) cnt[i] = 0u;
-    uint32_t base[kGM];
-#pragma unroll
-    for (int g = 0; g < kGM; ++g) base[g] = kNoBase;
-    const float ne0 = -a.e0f * a.inv_dr;
-    const float lo2 = T.e2f[0] - T.guard[0];
-    const float hi2 = T.e2f[a.nb] + T.guard[a.nb];
-    const unsigned nbu = (unsigned)a.nb;
+    for (int i = c.lane; i < kGM * kMaxBins; i += 64) c.cnt[i] = 0u;
+    wave_sync();
 
-    for (int sweep = 0; sweep < 2; ++sweep) {
-        Staged st[kStage];
-        // prologue: tile 0
-#pragma unroll
-        for (int s = 0; s < kStage; ++s) {
-            const int i = s * 64 * kNW + threadIdx.x;
-            stage_load<SINGLE>(st[s], S, np, total, i, a.pf);
-            stage_store<SINGLE>(st[s], tiles + i, cst, cshift, a.g.hf);
-        }
-        __syncthreads();
-        int buf = 0;
-        for (int t = 0; t < total; t += kTile) {
-            const float4* cur = tiles + buf * kTile;
-            const bool more = t + kTile < total;
-            if (more) {
-#pragma unroll
-                for (int s = 0; s < kStage; ++s)
-                    stage_load<SINGLE>(st[s], S, np, total, t + kTile + s * 64 * kNW + (int)threadIdx.x, a.pf);
-            }
-            const int nt = min(kTile, total - t);
-#pragma unroll 2
-            for (int u = 0; u < kUT; ++u) {
-                const int i = u * 64 + lane;
-                const float4 c = cur[i];
-                const bool valid = i < nt;
-                const uint32_t entry = __float_as_uint(c.w);
-#pragma unroll
-                for (int g = 0; g < kGM; ++g) {
-                    if (g >= ng) break;
-                    float dx = c.x - px[g], dy = c.y - py[g], dz = c.z - pz[g];
-                    if constexpr (SINGLE) {
-                        dx -= a.g.boxf * rintf(dx * a.inv_boxf);
-                        dy -= a.g.boxf * rintf(dy * a.inv_boxf);
-                        dz -= a.g.boxf * rintf(dz * a.inv_boxf);
-                    }
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    int bb;
-                    bool near;
-                    if constexpr (UNIFORM) {
-                        const float uu = fmaf(__builtin_amdgcn_sqrtf(r2), a.inv_dr, ne0);
-                        const float fl = floorf(uu);
-                        bb = (int)fl;
-                        const float fr = uu - fl;
-                        // guard bands of the edges e_0 .. e_nb: bb in [-1, nb]
-                        near = (fr < a.delta || fr > 1.0f - a.delta) && (unsigned)(bb + 1) <= nbu + 1u;
-                    } else {
-                        bb = -1;
-                        near = false;
-                        if (r2 >= lo2 && r2 < hi2) {
-                            for (int e = 0; e <= a.nb; ++e) {
-                                bb += r2 >= T.e2f[e];
-                                near |= fabsf(r2 - T.e2f[e]) < T.guard[e];
-                            }
-                        }
-                    }
-                    int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
-                    if (valid && near) {
-                        b = exact_pair<SINGLE>(a.pd, cs + wave + kNW * g, cstart, entry, mask, cshift, cx, cy,
-                                               cz, a.g.k, a.g.nc, a.g.box, a.nb, T.e2);
-                    }
-                    if (b >= 0) {
-                        if (sweep == 0) {
-                            atomicAdd(&cnt[g * kMaxBins + b], 1u);
-                        } else if (base[g] != kNoBase) {
-                            // the LDS unit serves the lanes of one atomic in a
-                            // fixed order, so the lists are the same on every run
-                            const uint32_t pos = atomicAdd(&cnt[g * kMaxBins + b], 1u);
-                            a.list[base[g] + pos] = entry;
-                        }
-                    }
-                }
-            }
-            if (more) {
-#pragma unroll
-                for (int s = 0; s < kStage; ++s)
-                    stage_store<SINGLE>(st[s], tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, cst,
-                                        cshift, a.g.hf);
-            }
-            __syncthreads();
-            buf ^= 1;
-        }
-        if (sweep == 1) break;
+    bin_sweep<0, SINGLE, UNIFORM>(a, c, px, py, pz, base);
 
-        // counts -> one allocation per wavefront; cnt becomes the offset of each
-        // bin inside its primary's allocation
-        wave_sync();
-        uint32_t tot[kGM], cl[kGM], ex[kGM];
-        uint32_t sum = 0;
+    // counts -> one allocation per wavefront; cnt becomes the offset of each
+    // bin inside its primary's allocation
+    wave_sync();
+    const int lane = c.lane;
+    uint32_t tot[kGM], cl[kGM], ex[kGM];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int g = 0; g < kGM; ++g) {
+        tot[g] = cl[g] = ex[g] = 0;
+        if (g >= c.ng) continue;
+        const int cv = lane < a.nb ? (int)c.cnt[g * kMaxBins + lane] : 0;
+        int incl = cv;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        tot[g] = (uint32_t)__shfl(incl, 63, 64);
+        cl[g] = (uint32_t)cv;
+        ex[g] = (uint32_t)(incl - cv);
+        if (lane < a.nb) c.cnt[g * kMaxBins + lane] = ex[g];
+        sum += tot[g];
+    }
+    if (c.ng > 0) {
+        const int64_t pl0 = c.cs + c.wave - a.p_begin;
+        const int slot = (int)(pl0 % kSlots);
+        const unsigned long long region = a.capacity / kSlots;
+        unsigned long long b0 = 0;
+        if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
+        b0 = __shfl(b0, 0, 64);
+        const bool ok = b0 + sum <= region;
+        if (!ok && lane == 0) atomicOr(a.overflow, 1);
+        uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
 #pragma unroll
         for (int g = 0; g < kGM; ++g) {
-            tot[g] = cl[g] = ex[g] = 0;
-            if (g >= ng) continue;
-            const int c = lane < a.nb ? (int)cnt[g * kMaxBins + lane] : 0;
-            int incl = c;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int v = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += v;
+            if (g >= c.ng) continue;
+            const int64_t pl = c.cs + c.wave + kNW * g - a.p_begin;
+            if (lane < a.nb) {
+                a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
+                a.boff[pl * a.nb + lane] = ok ? run + ex[g] : 0u;
             }
-            tot[g] = (uint32_t)__shfl(incl, 63, 64);
-            cl[g] = (uint32_t)c;
-            ex[g] = (uint32_t)(incl - c);
-            if (lane < a.nb) cnt[g * kMaxBins + lane] = ex[g];
-            sum += tot[g];
+            if (ok) base[g] = run;
+            run += tot[g];
         }
-        if (ng > 0) {
-            const int64_t pl0 = cs + wave - a.p_begin;
-            const int slot = (int)(pl0 % kSlots);
-            const unsigned long long region = a.capacity / kSlots;
-            unsigned long long b0 = 0;
-            if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
-            b0 = __shfl(b0, 0, 64);
-            const bool ok = b0 + sum <= region;
-            if (!ok && lane == 0) atomicOr(a.overflow, 1);
-            uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
-#pragma unroll
-            for (int g = 0; g < kGM; ++g) {
-                if (g >= ng) continue;
-                const int64_t pl = cs + wave + kNW * g - a.p_begin;
-                if (lane < a.nb) {
-                    a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
-                    a.boff[pl * a.nb + lane] = ok ? run + ex[g] : 0u;
-                }
-                if (ok) base[g] = run;
-                run += tot[g];
-            }
-        }
-        wave_sync();
     }
+    wave_sync();
+
+    bin_sweep<1, SINGLE, UNIFORM>(a, c, px, py, pz, base);
 }
 
 // ---------------------------------------------------------------- harmonics

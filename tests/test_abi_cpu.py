@@ -56,7 +56,6 @@ def _create(lib, **kw):
     (dict(lmax=13), T.TPCF_ERR_RANGE),
     (dict(lmax=-1), T.TPCF_ERR_RANGE),
     (dict(precision=4), T.TPCF_ERR_ARG),
-    (dict(lmax=12, edges=np.linspace(0, 40, 33), precision=2), T.TPCF_ERR_RANGE),
     (dict(grid_refine=5), T.TPCF_ERR_RANGE),
     (dict(flags=8), T.TPCF_ERR_ARG),
     (dict(edges=np.linspace(0, 40, 34)), T.TPCF_ERR_RANGE),
@@ -65,6 +64,17 @@ def test_invalid_configs_rejected_before_device(lib, kw, expect):
     rc, h = _create(lib, **kw)
     assert rc == expect
     assert not h.value
+
+
+def test_largest_config_fits_every_precision(lib):
+    # 32 bins at lmax 12 is the largest operand: every precision plans its
+    # contraction within LDS, so creation fails only for want of a device
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    for prec in range(4):
+        rc, h = _create(lib, lmax=12, edges=np.linspace(0, 40, 33), precision=prec)
+        assert rc == T.TPCF_ERR_DEVICE, prec
 
 
 def test_null_arguments(lib):
