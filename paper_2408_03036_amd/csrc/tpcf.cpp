@@ -77,7 +77,7 @@ struct tpcf_handle_s {
     std::vector<int64_t> pt_off;
     std::vector<double> n_data;
     bool unit_w = true;
-    DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pd, d_perm,
+    DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
         d_catid, d_flag, d_istart, d_icell, d_icat;
     std::vector<int> item_cat;       // [ncat+1] first work item of each catalogue
 
@@ -504,6 +504,7 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_orig, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pf, sizeof(float4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pw, sizeof(float) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_pa, sizeof(float4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pd, sizeof(double4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_perm, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_catid, sizeof(int) * N)) != TPCF_OK) return st;
@@ -521,7 +522,7 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     HIPCHK(launch_grid_order(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_tmp),
                              P<int>(h->d_orig), h->stream));
     HIPCHK(launch_grid_fill(d_pos, d_w, N, P<int>(h->d_orig), P<int>(h->d_cellid), h->g, P<float4>(h->d_pf),
-                            P<float>(h->d_pw), P<double4>(h->d_pd), P<int>(h->d_perm), P<int>(h->d_catid),
+                            P<float>(h->d_pw), P<float4>(h->d_pa), P<double4>(h->d_pd), P<int>(h->d_perm), P<int>(h->d_catid),
                             h->stream));
     // work items of the binning pass: blocks of up to kItemPrims primaries of one cell
     const int64_t nitems_max = M + N / kItemPrims + 1;
@@ -661,7 +662,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     }
     AlmArgs a{};
     a.pf = P<float4>(h->d_pf);
-    a.pw = P<float>(h->d_pw);
+    a.pa = P<float4>(h->d_pa);
     a.pd = P<double4>(h->d_pd);
     a.catid = P<int>(h->d_catid);
     a.pt_off = P<int64_t>(h->d_pt_off);
@@ -880,7 +881,7 @@ void tpcf_destroy(tpcf_handle h) {
     DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_runs, &h->d_shift_f, &h->d_goff,
                      &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
                      &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
-                     &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_lcursor, &h->d_boff,
+                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag};
     for (DevBuf* b : all) release(h, *b);

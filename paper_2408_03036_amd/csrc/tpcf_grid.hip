@@ -106,7 +106,7 @@ __global__ void k_grid_order(const int* __restrict__ cellid, int64_t n,
 __global__ void k_grid_fill(const double* __restrict__ pos, const double* __restrict__ w,
                             int64_t n, const int* __restrict__ orig,
                             const int* __restrict__ cellid, Grid g, float4* __restrict__ pf,
-                            float* __restrict__ pw, double4* __restrict__ pd,
+                            float* __restrict__ pw, float4* __restrict__ pa, double4* __restrict__ pd,
                             int* __restrict__ perm, int* __restrict__ catid) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -131,6 +131,7 @@ __global__ void k_grid_fill(const double* __restrict__ pos, const double* __rest
     q.w = (float)cz;
     pf[s] = q;
     pw[s] = (float)wi;
+    pa[s] = make_float4(q.x, q.y, q.z, (float)wi);
     pd[s] = make_double4(x, y, z, wi);
     perm[i] = (int)s;
     catid[s] = cat;
@@ -217,11 +218,11 @@ hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, con
 }
 
 hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const int* orig,
-                            const int* cellid, Grid g, float4* pf, float* pw, double4* pd,
+                            const int* cellid, Grid g, float4* pf, float* pw, float4* pa, double4* pd,
                             int* perm, int* catid, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grid_fill, dim3(nblk(n, 256)), dim3(256), 0, s, pos, w, n, orig, cellid,
-                       g, pf, pw, pd, perm, catid);
+                       g, pf, pw, pa, pd, perm, catid);
     return hipGetLastError();
 }
 

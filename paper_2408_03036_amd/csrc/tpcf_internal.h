@@ -58,7 +58,7 @@ hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, i
 hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, const int* tmp_idx,
                              int* orig, hipStream_t s);
 hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const int* orig,
-                            const int* cellid, Grid g, float4* pf, float* pw, double4* pd,
+                            const int* cellid, Grid g, float4* pf, float* pw, float4* pa, double4* pd,
                             int* perm, int* catid, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
 // Work items of the binning pass: each cell's primaries in blocks of kItemPrims.
@@ -103,8 +103,8 @@ hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);
 size_t pair_bin_lds_bytes(int npmax);
 
 struct AlmArgs {
-    const float4* pf;
-    const float* pw;
+    const float4* pf;        // sorted (xr, yr, zr, iz) cell-relative FP32
+    const float4* pa;        // sorted (xr, yr, zr, w): one 16-byte gather per neighbour
     const double4* pd;
     const int* catid;
     const int64_t* pt_off;

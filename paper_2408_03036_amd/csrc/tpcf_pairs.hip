@@ -668,24 +668,22 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
     uint32_t e0 = n > 0 ? a.list[off] : 0u;
     uint32_t e1 = n > 1 ? a.list[off + 1] : 0u;
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float w0f = 0.f;
     double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
     if (n > 0) {
         const int64_t j = cstart + (int64_t)(e0 & mask);
-        if constexpr (sizeof(T) == 4) { q0 = a.pf[j]; w0f = a.pw[j]; } else { d0 = a.pd[j]; }
+        if constexpr (sizeof(T) == 4) q0 = a.pa[j]; else d0 = a.pd[j];
     }
     for (uint32_t t = 0; t < n; ++t) {
         const uint32_t e2 = t + 2 < n ? a.list[off + t + 2] : 0u;
         float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float w1f = 0.f;
         double4 d1 = make_double4(0.0, 0.0, 0.0, 0.0);
         if (t + 1 < n) {
             const int64_t j = cstart + (int64_t)(e1 & mask);
-            if constexpr (sizeof(T) == 4) { q1 = a.pf[j]; w1f = a.pw[j]; } else { d1 = a.pd[j]; }
+            if constexpr (sizeof(T) == 4) q1 = a.pa[j]; else d1 = a.pd[j];
         }
         T x, y, z, w;
         if constexpr (sizeof(T) == 4) {
-            w = w0f;
+            w = q0.w;
             float dx = q0.x - P32.x, dy = q0.y - P32.y, dz = q0.z - P32.z;
             if (a.g.single) {
                 dx -= a.g.boxf * rintf(dx / a.g.boxf);
@@ -717,7 +715,6 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
         e0 = e1;
         e1 = e2;
         q0 = q1;
-        w0f = w1f;
         d0 = d1;
     }
     if (!active) return;
