@@ -15,7 +15,7 @@
  * Only tests/, the package's smoke() and the benchmark's CPU-baseline leg may
  * load this file's library. It shares no code with the GPU library.
  *
- * Readings taken where the paper is silent (each listed in the design doc):
+ * Readings taken where the paper is silent:
  *  - bins are half-open [e_b, e_{b+1}); a pair is in bin b iff
  *    e_b^2 <= r^2 < e_{b+1}^2 with r^2 = dx*dx + dy*dy + dz*dz evaluated
  *    left to right in double (no fused multiply-add); r = 0 pairs are dropped;

@@ -1,0 +1,119 @@
+"""Parity at full workload sizes, through the C ABI, in the configurations
+the benchmark runs.
+
+The oracle cannot form the multipoles of a 10^5-point catalogue in test time,
+so at these sizes it checks what it can compute primary by primary: a_lm(p, b)
+of a slice of primaries (Sec. 4.2, eq. (alm)) needs only those primaries'
+neighbours. The batched run of 64 catalogues is checked by properties that hold
+at any size: each catalogue of the batch equals the same catalogue run alone,
+bit for bit; the mixed path agrees with the FP64 path within the split-BF16
+tolerance; and one catalogue's a_lm slice matches the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2408_03036_amd import catalogs as C
+from paper_2408_03036_amd import tpcf as T
+
+pytestmark = pytest.mark.gpu
+
+SLICE = 64  # primaries whose a_lm the oracle recomputes
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    T.load()
+    return _t
+
+
+def alm_slice_error(torch, pos, box, edges, lmax, prec, first):
+    """Max |a_lm(GPU) - a_lm(oracle)| / max |a_lm(oracle)| over a slice of primaries."""
+    h = T.Handle(box, edges, lmax, precision=prec)
+    h.build_grid(torch.from_numpy(pos).cuda())
+    h.alm_accumulate()
+    got = h.get_alm(first, SLICE).cpu().numpy()
+    h.sync()
+    h.close()
+    ref = O.estimate(pos, box, edges, lmax, prim_first=first, prim_count=SLICE, want_alm=True,
+                     want_nnn=False).alm
+    s1 = lmax + 1
+    mask = np.tril(np.ones((s1, s1), dtype=bool))  # m <= l
+    return float(np.abs(got[..., mask] - ref[..., mask]).max() / np.abs(ref[..., mask]).max())
+
+
+def zeldovich_host(torch, n, box, sigma, f, seed):
+    return C.zeldovich_torch(n, box, sigma, f, seed, grid=256, device="cuda").cpu().numpy()
+
+
+# 10^5 points in a 1000 Mpc/h box, 10 bins over [20, 120], lmax = 10.
+@pytest.mark.parametrize("prec,tol", [(T.PREC_FP64, 1e-12), (T.PREC_FP32, 1e-5)])
+def test_alm_slice_100k(torch, prec, tol):
+    say(f"  100k catalogue, precision {prec}")
+    pos = zeldovich_host(torch, 100_000, 1000.0, 6.0, 0.8, C.catalogue_seed(1))
+    err = alm_slice_error(torch, pos, 1000.0, np.linspace(20.0, 120.0, 11), 10, prec, 31_337)
+    say(f"  a_lm slice rel err {err:.3e}")
+    assert err < tol
+
+
+# 4x10^5 points in a 1500 Mpc/h box, 12 bins over [10, 130], lmax = 10: the
+# mixed path's pair pass (FP32) that feeds the split-BF16 contraction.
+def test_alm_slice_400k_mixed(torch):
+    say("  400k catalogue, split-BF16 path")
+    pos = zeldovich_host(torch, 400_000, 1500.0, 5.0, 0.8, C.catalogue_seed(2))
+    err = alm_slice_error(torch, pos, 1500.0, np.linspace(10.0, 130.0, 13), 10,
+                          T.PREC_MIXED_BF16X3, 250_001)
+    say(f"  a_lm slice rel err {err:.3e}")
+    assert err < 1e-5
+
+
+def test_batched_64_catalogues(torch):
+    """The benchmark's batch: 64 catalogues, sizes log-uniform in [5e4, 3e5]."""
+    box, edges, lmax = 1000.0, np.linspace(20.0, 120.0, 11), 10
+    mults = O.all_multipoles(lmax, 2)
+    sizes = C.log_uniform_sizes(64, 50_000, 300_000, C.BASE_SEED + 777)
+    say(f"  generating 64 catalogues ({int(sizes.sum())} points)")
+    cats = [C.zeldovich_torch(int(n), box, 6.0, 0.8, C.catalogue_seed(i), grid=256, device="cuda")
+            for i, n in enumerate(sizes)]
+    P = torch.cat(cats, dim=0).contiguous()
+
+    def batch(prec):
+        h = T.Handle(box, edges, lmax, precision=prec, workspace_limit=96 << 30)
+        out = h.run_catalogs(sizes, sizes, P, None, mults)
+        h.sync()
+        n = h.pair_count()
+        h.close()
+        return out.cpu().numpy(), n
+
+    say("  batched split-BF16")
+    mixed, np_mixed = batch(T.PREC_MIXED_BF16X3)
+    say("  batched FP64")
+    fp64, np_fp64 = batch(T.PREC_FP64)
+    assert np_mixed == np_fp64
+    err = float(np.abs(mixed - fp64).max() / np.abs(fp64).max())
+    say(f"  mixed vs FP64 rel err {err:.3e}")
+    assert err < 1e-4
+
+    for i in (0, 63):
+        h = T.Handle(box, edges, lmax, precision=T.PREC_MIXED_BF16X3)
+        h.build_grid(cats[i])
+        h.alm_accumulate()
+        h.contract()
+        single = h.multipoles(mults)
+        h.sync()
+        h.close()
+        assert np.array_equal(single.cpu().numpy(), mixed[i]), i
+
+    pos0 = cats[0].cpu().numpy()
+    err = alm_slice_error(torch, pos0, box, edges, lmax, T.PREC_FP64, 1000)
+    say(f"  catalogue 0 a_lm slice rel err {err:.3e}")
+    assert err < 1e-12
