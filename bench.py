@@ -89,6 +89,23 @@ def time_steps(torch, h, sizes, pos, mults, steps, warmup):
     return dt, ms, nl, npairs, out
 
 
+def measured_traffic(kernel_sources):
+    """HBM bytes per launch of the dominant kernel, from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes summarised in profiles/ (scaled by the copy-kernel
+    calibration recorded there). None once the kernel's sources differ from the
+    ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_pair_alm_batched64_lmax10_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", kernel_sources):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def cpu_baseline(pos_np, box, edges, lmax, target_s=15.0):
     """Times the FP64 CPU oracle on a bounded sample of primaries of one
     catalogue (all host threads), scaled to pairs/s."""
@@ -161,10 +178,15 @@ def main():
     launches_per_step = nl[2] / args.steps
     flop_launch = npairs * flop_per_pair(lmax) / launches_per_step
     achieved = flop_launch / t_alm
+    traffic = None
+    if args.ncat == 64 and prec_id != T.PREC_FP64:
+        traffic = measured_traffic(["paper_2408_03036_amd/csrc/tpcf_pairs.hip",
+                                    "paper_2408_03036_amd/csrc/tpcf_internal.h"])
     roof = {"kernel": "k_pair_alm<float,10> (harmonic pass)", "bound": "alu",
             "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-            "flop_per_pair": flop_per_pair(lmax), "avg_launch_ms": t_alm * 1e3}
+            "frac": achieved / PEAK_FP32_VALU, "traffic": traffic,
+            "flop_per_pair": flop_per_pair(lmax), "avg_launch_ms": t_alm * 1e3,
+            "launches_per_step": launches_per_step}
     stages = {"grid_ms": ms[0] / args.steps, "pair_bin_ms": ms[1] / args.steps,
               "pair_alm_ms": ms[2] / args.steps, "contract_ms": ms[3] / args.steps,
               "finalize_ms": ms[4] / args.steps}
