@@ -540,8 +540,11 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     return TPCF_OK;
 }
 
+// Bytes per hit in the neighbour lists.
+size_t list_elem_bytes(tpcf_handle h) { return h->fp64 ? sizeof(uint32_t) : sizeof(float4); }
+
 // Splits every catalogue into subchunks of kc primaries and groups whole
-// subchunks into chunks whose a_lm operand fits the workspace share.
+// subchunks into chunks whose a_lm operand and hit lists fit the workspace share.
 tpcf_status plan_chunks(tpcf_handle h) {
     const int64_t N = h->npts;
     const size_t elem = h->fp64 ? 8 : 4;
@@ -553,8 +556,13 @@ tpcf_status plan_chunks(tpcf_handle h) {
     int64_t maxn = 0;
     for (int c = 0; c < h->ncat; ++c) maxn = std::max(maxn, h->pt_off[c + 1] - h->pt_off[c]);
     const double hits = std::min((double)maxn, maxn / L3 * shell);
-    const double list_per = 4.0 * (2.0 * hits + 64.0);
-    int64_t budget = h->limit / 3;
+    // hit lists: 4-byte entries (FP64 path) or 16-byte records (FP32 paths);
+    // room for 1.3x the densest catalogue's expected hits (a list that
+    // overflows is rebuilt with twice the room)
+    const double lelem = list_elem_bytes(h);
+    const double hits_room = 1.3 * hits + 64.0;
+    const double list_per = lelem * hits_room;
+    int64_t budget = h->limit / 2;
     int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
     cap = std::min<int64_t>(cap, 1 << 20);
     cap = std::max<int64_t>(h->kc, cap / h->kc * h->kc);
@@ -583,12 +591,12 @@ tpcf_status plan_chunks(tpcf_handle h) {
     int64_t maxch = 0;
     for (auto& ch : h->chunks) maxch = std::max(maxch, ch.p_end - ch.p_begin);
     h->ldA = (maxch + 63) / 64 * 64;
-    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, (double)maxch * (2.0 * hits + 64.0)));
+    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, (double)maxch * hits_room));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_cnt, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_A, (size_t)h->nb * h->NV * h->ldA * elem)) != TPCF_OK) return st;
-    if ((st = ensure(h, h->d_list, sizeof(uint32_t) * h->list_cap)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_lcursor, sizeof(unsigned long long) * kSlots * 16)) != TPCF_OK) return st;
     // subchunk tables: per chunk, chunk-relative starts are uploaded on demand
     if ((st = ensure(h, h->d_subs, sizeof(int) * (nsub + 1) + 64)) != TPCF_OK) return st;
@@ -623,7 +631,9 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         b.guard = P<float>(h->d_guard);
         b.p_begin = ch.p_begin;
         b.p_end = ch.p_end;
-        b.list = P<uint32_t>(h->d_list);
+        b.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
+        b.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
+        b.pw = P<float>(h->d_pw);
         b.cursor = P<unsigned long long>(h->d_lcursor);
         b.capacity = h->list_cap;
         b.boff = P<uint32_t>(h->d_boff);
@@ -658,7 +668,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         unsigned long long ncap = std::min<unsigned long long>(4000000000ull, h->list_cap * 2);
         if (ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
         h->list_cap = ncap;
-        if ((st = ensure(h, h->d_list, sizeof(uint32_t) * h->list_cap)) != TPCF_OK) return st;
+        if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
     }
     AlmArgs a{};
     a.pf = P<float4>(h->d_pf);
@@ -671,7 +681,8 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     a.lmax = h->lmax;
     a.p_begin = ch.p_begin;
     a.p_end = ch.p_end;
-    a.list = P<uint32_t>(h->d_list);
+    a.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
+    a.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
     a.boff = P<uint32_t>(h->d_boff);
     a.cnt = P<uint32_t>(h->d_cnt);
     a.A = h->d_A.p;

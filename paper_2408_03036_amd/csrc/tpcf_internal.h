@@ -71,6 +71,7 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
 // Pair pass (tpcf_pairs.hip)
 struct BinArgs {
     const float4* pf;        // sorted (xr, yr, zr, iz) cell-relative FP32
+    const float* pw;         // sorted FP32 weights
     const double4* pd;       // sorted (x, y, z, w) FP64 wrapped
     const int* catid;        // sorted catalogue id
     const int* cell_start;   // [ncat*ncell+1]
@@ -83,7 +84,8 @@ struct BinArgs {
     const float* e2f;        // [nb+1] squared edges (FP32)
     const float* guard;      // [nb+1] FP32 guard band around each squared edge
     int64_t p_begin, p_end;  // primaries (sorted indices) of this chunk
-    uint32_t* list;          // hit lists of the chunk
+    uint32_t* list;          // hit lists of the chunk (list entries), or
+    float4* rec;             // hit records (dx, dy, dz, w_j) when not null (FP32 paths)
     unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each
     unsigned long long capacity;
     uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists
@@ -112,7 +114,8 @@ struct AlmArgs {
     int nb;
     int lmax;
     int64_t p_begin, p_end;
-    const uint32_t* list;
+    const uint32_t* list;    // list entries (FP64 path)
+    const float4* rec;       // hit records (dx, dy, dz, w_j) (FP32 paths)
     const uint32_t* boff;
     const uint32_t* cnt;
     void* A;                 // [nb][nvalues][ldA] float or double

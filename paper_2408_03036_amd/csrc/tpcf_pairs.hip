@@ -267,15 +267,16 @@ static_assert(kGM * kNW == kItemPrims, "item size");
 // and its index, held in registers while the previous tile is tested.
 struct Staged {
     float4 q;
+    float w;
     float sx, sy, zo;
     int code;
     uint32_t j;
     bool ok;
 };
 
-template <bool SINGLE>
+template <bool SINGLE, bool REC>
 __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, int total, int g,
-                                           const float4* pf) {
+                                           const float4* pf, const float* pw) {
     st.ok = g < total;
     if (st.ok) {
         const int r = find_piece(S.pref, np, g);
@@ -286,31 +287,38 @@ __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, 
         st.zo = rc.w;
         st.code = S.code[r] & 0xffff;
         st.q = pf[st.j];
+        st.w = REC ? pw[st.j] : 0.f;
     }
 }
 
-// Writes a staged candidate in the home cell's frame: (x, y, z, list entry),
-// entry = catalogue-relative index | stencil code << cshift.
+// Writes a staged candidate in the home cell's frame, (x, y, z, w), and its
+// list entry = catalogue-relative index | stencil code << cshift.
 template <bool SINGLE>
-__device__ __forceinline__ void stage_store(const Staged& st, float4* dst, uint32_t cst, int cshift, float hf) {
+__device__ __forceinline__ void stage_store(const Staged& st, float4* dst, uint32_t* dent, uint32_t cst,
+                                            int cshift, float hf) {
     if (!st.ok) return;
     float4 v;
+    uint32_t e;
     if constexpr (SINGLE) {
-        v = make_float4(st.q.x, st.q.y, st.q.z, __uint_as_float(st.j - cst));
+        v = make_float4(st.q.x, st.q.y, st.q.z, st.w);
+        e = st.j - cst;
     } else {
         const int oz = (int)(st.q.w + st.zo);
         v.x = st.q.x + st.sx;
         v.y = st.q.y + st.sy;
         v.z = fmaf((float)oz, hf, st.q.z);
-        v.w = __uint_as_float((st.j - cst) | ((uint32_t)(st.code + oz) << cshift));
+        v.w = st.w;
+        e = (st.j - cst) | ((uint32_t)(st.code + oz) << cshift);
     }
     *dst = v;
+    *dent = e;
 }
 
 // State of one work item shared by its two sweeps.
 struct ItemCtx {
     const Pieces* S;
-    float4* tiles;
+    float4* tiles;          // [2][kTile] candidates (x, y, z, w) in the home cell's frame
+    uint32_t* tent;         // [2][kTile] their list entries
     const BinTables* T;
     uint32_t* cnt;          // this wavefront's [kGM][kMaxBins] counters / offsets
     int np, total;
@@ -321,8 +329,9 @@ struct ItemCtx {
 
 // One sweep over the item's candidates. SWEEP 0 counts the hits of every
 // (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
-// bin), the offsets having been prepared in cnt.
-template <int SWEEP, bool SINGLE, bool UNIFORM>
+// bin), the offsets having been prepared in cnt: as a list entry, or with REC
+// as the record (dx, dy, dz, w_j) that the FP32 harmonic pass streams.
+template <int SWEEP, bool SINGLE, bool UNIFORM, bool REC>
 __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, const float (&px)[kGM],
                                           const float (&py)[kGM], const float (&pz)[kGM],
                                           const uint32_t (&base)[kGM]) {
@@ -335,18 +344,20 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
 #pragma unroll
     for (int s = 0; s < kStage; ++s) {
         const int i = s * 64 * kNW + threadIdx.x;
-        stage_load<SINGLE>(st[s], *c.S, c.np, c.total, i, a.pf);
-        stage_store<SINGLE>(st[s], c.tiles + i, c.cst, c.cshift, a.g.hf);
+        stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, i, a.pf, a.pw);
+        stage_store<SINGLE>(st[s], c.tiles + i, c.tent + i, c.cst, c.cshift, a.g.hf);
     }
     __syncthreads();
     int buf = 0;
     for (int t = 0; t < c.total; t += kTile) {
         const float4* cur = c.tiles + buf * kTile;
+        const uint32_t* cure = c.tent + buf * kTile;
         const bool more = t + kTile < c.total;
         if (more) {
 #pragma unroll
             for (int s = 0; s < kStage; ++s)
-                stage_load<SINGLE>(st[s], *c.S, c.np, c.total, t + kTile + s * 64 * kNW + (int)threadIdx.x, a.pf);
+                stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, t + kTile + s * 64 * kNW + (int)threadIdx.x,
+                                        a.pf, a.pw);
         }
         const int nt = min(kTile, c.total - t);
 #pragma unroll 2
@@ -354,7 +365,7 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
             const int i = u * 64 + c.lane;
             const float4 q = cur[i];
             const bool valid = i < nt;
-            const uint32_t entry = __float_as_uint(q.w);
+            const uint32_t entry = cure[i];
 #pragma unroll
             for (int g = 0; g < kGM; ++g) {
                 if (g >= c.ng) break;
@@ -395,15 +406,20 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
                     // the LDS unit serves the lanes of one atomic in a fixed
                     // order, so the lists are the same on every run
                     const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
-                    a.list[base[g] + pos] = entry;
+                    if constexpr (REC) {
+                        a.rec[base[g] + pos] = make_float4(dx, dy, dz, q.w);
+                    } else {
+                        a.list[base[g] + pos] = entry;
+                    }
                 }
             }
         }
         if (more) {
 #pragma unroll
             for (int s = 0; s < kStage; ++s)
-                stage_store<SINGLE>(st[s], c.tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, c.cst,
-                                    c.cshift, a.g.hf);
+                stage_store<SINGLE>(st[s], c.tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x,
+                                    c.tent + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, c.cst, c.cshift,
+                                    a.g.hf);
         }
         __syncthreads();
         buf ^= 1;
@@ -418,7 +434,7 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
 // are staged in LDS once per tile for the whole workgroup, in the home cell's
 // frame, and every wavefront tests them against its primaries (kGM at most),
 // double-buffered so that the loads of the next tile overlap the tests.
-template <bool SINGLE, bool UNIFORM>
+template <bool SINGLE, bool UNIFORM, bool REC>
 __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     extern __shared__ unsigned char smem[];
     BinTables& T = *reinterpret_cast<BinTables*>(smem);
@@ -430,6 +446,8 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     size_t off = (sizeof(BinTables) + 15) / 16 * 16;
     float4* tiles = reinterpret_cast<float4*>(smem + off);
     off += sizeof(float4) * 2 * kTile;
+    uint32_t* tent = reinterpret_cast<uint32_t*>(smem + off);
+    off += sizeof(uint32_t) * 2 * kTile;
     Pieces S = pieces_view(smem + off, a.npmax);
     off += pieces_lds_bytes(a.npmax);
     ItemCtx c;
@@ -439,6 +457,7 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     c.T = &T;
     c.S = &S;
     c.tiles = tiles;
+    c.tent = tent;
 
     const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
     if (item >= a.item_hi) return;
@@ -480,7 +499,7 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     for (int i = c.lane; i < kGM * kMaxBins; i += 64) c.cnt[i] = 0u;
     wave_sync();
 
-    bin_sweep<0, SINGLE, UNIFORM>(a, c, px, py, pz, base);
+    bin_sweep<0, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
 
     // counts -> one allocation per wavefront; cnt becomes the offset of each
     // bin inside its primary's allocation
@@ -528,7 +547,7 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     }
     wave_sync();
 
-    bin_sweep<1, SINGLE, UNIFORM>(a, c, px, py, pz, base);
+    bin_sweep<1, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
 }
 
 // ---------------------------------------------------------------- harmonics
@@ -626,10 +645,6 @@ template <typename T, int LMAX, int G>
 __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
     using AC = Acc<T, LMAX, G>;
     constexpr int NV = n_values(LMAX);
-    __shared__ float sh[kMaxCodes * 3];
-    for (int i = threadIdx.x; i < a.ncodes * 3; i += blockDim.x) sh[i] = a.shift_f[i];
-    __syncthreads();
-
     const int lane = lane_id();
     const int64_t nprim = a.p_end - a.p_begin;
     const int64_t nblk64 = (nprim + 63) / 64;
@@ -652,54 +667,41 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
     for (int i = 0; i < (AC::NS > 0 ? AC::NS : 1); ++i) acc.s[i] = (T)0;
 
     uint32_t n = 0, off = 0;
-    int64_t cstart = 0;
-    float4 P32 = make_float4(0.f, 0.f, 0.f, 0.f);
-    double4 P64 = make_double4(0.0, 0.0, 0.0, 0.0);
     if (active) {
         n = a.cnt[pl * a.nb + b];
         off = a.boff[pl * a.nb + b];
-        cstart = a.pt_off[a.catid[p]];
-        if (sizeof(T) == 4) P32 = a.pf[p]; else P64 = a.pd[p];
     }
-    const uint32_t mask = a.g.idx_mask;
-    const int cshift = 32 - a.g.code_bits;
-    // Software pipeline: the list entry of hit t+2 and the point data of hit
-    // t+1 are in flight while hit t is accumulated.
-    uint32_t e0 = n > 0 ? a.list[off] : 0u;
-    uint32_t e1 = n > 1 ? a.list[off + 1] : 0u;
-    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (n > 0) {
-        const int64_t j = cstart + (int64_t)(e0 & mask);
-        if constexpr (sizeof(T) == 4) q0 = a.pa[j]; else d0 = a.pd[j];
-    }
-    for (uint32_t t = 0; t < n; ++t) {
-        const uint32_t e2 = t + 2 < n ? a.list[off + t + 2] : 0u;
-        float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        double4 d1 = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (t + 1 < n) {
-            const int64_t j = cstart + (int64_t)(e1 & mask);
-            if constexpr (sizeof(T) == 4) q1 = a.pa[j]; else d1 = a.pd[j];
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the binning pass wrote each hit as (dx, dy, dz, w_j); records
+        // two hits ahead are in flight while a hit is accumulated.
+        const float4* rec = a.rec + off;
+        float4 r0 = n > 0 ? rec[0] : make_float4(1.f, 0.f, 0.f, 0.f);
+        float4 r1 = n > 1 ? rec[1] : make_float4(1.f, 0.f, 0.f, 0.f);
+        for (uint32_t t = 0; t < n; ++t) {
+            const float4 r2 = t + 2 < n ? rec[t + 2] : make_float4(1.f, 0.f, 0.f, 0.f);
+            const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
+            const float inv = __builtin_amdgcn_rsqf(d2);
+            add_hit<T, LMAX, G>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
+            r0 = r1;
+            r1 = r2;
         }
-        T x, y, z, w;
-        if constexpr (sizeof(T) == 4) {
-            w = q0.w;
-            float dx = q0.x - P32.x, dy = q0.y - P32.y, dz = q0.z - P32.z;
-            if (a.g.single) {
-                dx -= a.g.boxf * rintf(dx / a.g.boxf);
-                dy -= a.g.boxf * rintf(dy / a.g.boxf);
-                dz -= a.g.boxf * rintf(dz / a.g.boxf);
-            } else {
-                const int code = (int)(e0 >> cshift);
-                dx += sh[3 * code];
-                dy += sh[3 * code + 1];
-                dz += sh[3 * code + 2];
-            }
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float inv = __builtin_amdgcn_rsqf(r2);
-            x = dx * inv; y = dy * inv; z = dz * inv;
-        } else {
-            w = d0.w;
+    } else {
+        // FP64: list entries two hits ahead and the point one hit ahead.
+        int64_t cstart = 0;
+        double4 P64 = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (active) {
+            cstart = a.pt_off[a.catid[p]];
+            P64 = a.pd[p];
+        }
+        const uint32_t mask = a.g.idx_mask;
+        uint32_t e0 = n > 0 ? a.list[off] : 0u;
+        uint32_t e1 = n > 1 ? a.list[off + 1] : 0u;
+        double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (n > 0) d0 = a.pd[cstart + (int64_t)(e0 & mask)];
+        for (uint32_t t = 0; t < n; ++t) {
+            const uint32_t e2 = t + 2 < n ? a.list[off + t + 2] : 0u;
+            double4 d1 = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (t + 1 < n) d1 = a.pd[cstart + (int64_t)(e1 & mask)];
             double dx = d0.x - P64.x, dy = d0.y - P64.y, dz = d0.z - P64.z;
             const double L = a.g.box, hL = 0.5 * a.g.box;
             dx = dx > hL ? dx - L : (dx < -hL ? dx + L : dx);
@@ -709,13 +711,11 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
             double inv = __builtin_amdgcn_rsq(r2);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
-            x = dx * inv; y = dy * inv; z = dz * inv;
+            add_hit<T, LMAX, G>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d0.w);
+            e0 = e1;
+            e1 = e2;
+            d0 = d1;
         }
-        add_hit<T, LMAX, G>(acc, x, y, z, w);
-        e0 = e1;
-        e1 = e2;
-        q0 = q1;
-        d0 = d1;
     }
     if (!active) return;
     T* A = reinterpret_cast<T*>(a.A);
@@ -764,16 +764,26 @@ hipError_t launch_alm_lmax(const AlmArgs& a, int fp64, hipStream_t s) {
 
 }  // namespace
 
-template <bool SINGLE, bool UNIFORM>
+template <bool SINGLE, bool UNIFORM, bool REC>
 hipError_t launch_bin_variant(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void*)k_pair_bin<SINGLE, UNIFORM>,
+        hipFuncSetAttribute((const void*)k_pair_bin<SINGLE, UNIFORM, REC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_pair_bin<SINGLE, UNIFORM>), dim3((unsigned)nblk), dim3(64 * kNW), lds, s, a);
+    hipLaunchKernelGGL((k_pair_bin<SINGLE, UNIFORM, REC>), dim3((unsigned)nblk), dim3(64 * kNW), lds, s, a);
     return hipGetLastError();
+}
+
+template <bool REC>
+hipError_t launch_bin_rec(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
+    if (a.g.single) {
+        return a.uniform ? launch_bin_variant<true, true, REC>(a, s, nblk, lds)
+                         : launch_bin_variant<true, false, REC>(a, s, nblk, lds);
+    }
+    return a.uniform ? launch_bin_variant<false, true, REC>(a, s, nblk, lds)
+                     : launch_bin_variant<false, false, REC>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
@@ -782,12 +792,7 @@ hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
     // a multiple of 8 blocks, so that the XCD remap is a permutation
     const int64_t nblk = (nitems + 7) / 8 * 8;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
-    if (a.g.single) {
-        return a.uniform ? launch_bin_variant<true, true>(a, s, nblk, lds)
-                         : launch_bin_variant<true, false>(a, s, nblk, lds);
-    }
-    return a.uniform ? launch_bin_variant<false, true>(a, s, nblk, lds)
-                     : launch_bin_variant<false, false>(a, s, nblk, lds);
+    return a.rec ? launch_bin_rec<true>(a, s, nblk, lds) : launch_bin_rec<false>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {
@@ -811,7 +816,8 @@ hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {
 }
 
 size_t pair_bin_lds_bytes(int npmax) {
-    return (sizeof(BinTables) + 15) / 16 * 16 + sizeof(float4) * 2 * kTile + pieces_lds_bytes(npmax) +
+    return (sizeof(BinTables) + 15) / 16 * 16 + (sizeof(float4) + sizeof(uint32_t)) * 2 * kTile +
+           pieces_lds_bytes(npmax) +
            sizeof(uint32_t) * kNW * kGM * kMaxBins;
 }
 
