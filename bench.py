@@ -169,6 +169,7 @@ def main():
                  workspace_limit=96 << 30)
     h.set_timing(True)
     dt, ms, nl, npairs, out = time_steps(torch, h, sizes, pos, mults, args.steps, args.warmup)
+    rebinned = h.rebinned_count() / max(args.steps + args.warmup, 1)
     h.close()
     value = npairs / dt
     cats_per_hour = args.ncat * 3600.0 / dt
@@ -235,6 +236,7 @@ def main():
                    "pairs_per_step": int(npairs), "parallelism": "single GPU"},
         "catalogs_per_hour": cats_per_hour,
         "stages_ms": stages,
+        "rebinned_primaries_per_step": rebinned,
         "roofline": roof,
         "contraction": contraction,
         "fp64_path": fp64,

@@ -163,6 +163,15 @@ tpcf_status tpcf_sync(tpcf_handle h);
 tpcf_status tpcf_pair_count(tpcf_handle h, int64_t* h_out);
 
 /*
+ * Primaries whose neighbours were binned a second time with exact counts since
+ * the handle was created. The binning pass gives each (primary, bin) a region
+ * sized from the local density its cell's stencil shows; a primary with more
+ * neighbours in some bin than its region holds (strong clustering) is redone
+ * with exact counts. Results do not depend on it; it only costs time.
+ */
+tpcf_status tpcf_rebinned_count(tpcf_handle h, int64_t* h_out);
+
+/*
  * Per-stage device time. With enable != 0 the handle records HIP events around
  * each stage it enqueues; tpcf_stage_times then returns, after tpcf_sync, the
  * summed milliseconds of the stages since the last reset and resets them:

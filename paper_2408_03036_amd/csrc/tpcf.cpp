@@ -91,6 +91,9 @@ struct tpcf_handle_s {
     float delta = 0.f;    // FP32 guard band in units of the bin width
     int64_t chunk_cap = 0;
     unsigned long long list_cap = 0;
+    DevBuf d_fix;
+    int64_t nfix_total = 0;   // primaries rebinned with exact counts (all chunks since creation)
+    double inv_vst = 0.0;     // 1 / stencil volume
     DevBuf d_list, d_lcursor, d_boff, d_cnt, d_A, d_subs, d_catsub, d_part, d_pself, d_G, d_S, d_nd,
         d_mult, d_coefG, d_coefS, d_lflag;
     int64_t ldA = 0;
@@ -408,6 +411,9 @@ tpcf_status plan_grid(tpcf_handle h, int64_t max_cat) {
         h->g.code_bits = cb;
         h->g.idx_mask = (uint32_t)((1ULL << (32 - cb)) - 1);
         h->runs = runs;
+        int64_t cells = 0;
+        for (const StencilRun& r : runs) cells += r.oz_hi - r.oz_lo + 1;
+        h->inv_vst = 1.0 / ((double)cells * hc * hc * hc);
         h->ncodes = K2 * K2 * K2;
         break;
     }
@@ -426,6 +432,7 @@ tpcf_status plan_grid(tpcf_handle h, int64_t max_cat) {
         h->g.code_bits = 1;
         h->g.idx_mask = 0x7fffffffu;
         h->runs = {{0, 0, 0, 0}};
+        h->inv_vst = 1.0 / (L * L * L);
         h->ncodes = 1;
     }
     // shift table
@@ -557,10 +564,15 @@ tpcf_status plan_chunks(tpcf_handle h) {
     for (int c = 0; c < h->ncat; ++c) maxn = std::max(maxn, h->pt_off[c + 1] - h->pt_off[c]);
     const double hits = std::min((double)maxn, maxn / L3 * shell);
     // hit lists: 4-byte entries (FP64 path) or 16-byte records (FP32 paths);
-    // room for 1.3x the densest catalogue's expected hits (a list that
-    // overflows is rebuilt with twice the room)
+    // room for the predicted bin regions of a primary of the densest
+    // catalogue (the binning kernel's margin), plus the rare exact rebins (a
+    // list that overflows is rebuilt with twice the room)
     const double lelem = list_elem_bytes(h);
-    const double hits_room = 1.3 * hits + 64.0;
+    double hits_room = 64.0;
+    for (int b = 0; b < h->nb; ++b) {
+        const double pred = std::min((double)maxn, maxn / L3 * h->vol[b]);
+        hits_room += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
+    }
     const double list_per = lelem * hits_room;
     int64_t budget = h->limit / 2;
     int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
@@ -594,6 +606,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, (double)maxch * hits_room));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_cnt, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_A, (size_t)h->nb * h->NV * h->ldA * elem)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
@@ -615,7 +628,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     if ((st = upload(h, h->d_subs, rel.data(), sizeof(int) * rel.size())) != TPCF_OK) return st;
     for (int attempt = 0; attempt < 6; ++attempt) {
         HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), kSlots * 16, 0ull, h->stream));
-        HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 1, 0, h->stream));
+        HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 2, 0, h->stream));  // overflow, fix-up count
         BinArgs b{};
         b.pf = P<float4>(h->d_pf);
         b.pd = P<double4>(h->d_pd);
@@ -633,12 +646,16 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         b.p_end = ch.p_end;
         b.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
         b.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
-        b.pw = P<float>(h->d_pw);
+        b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
         b.cursor = P<unsigned long long>(h->d_lcursor);
         b.capacity = h->list_cap;
         b.boff = P<uint32_t>(h->d_boff);
         b.cnt = P<uint32_t>(h->d_cnt);
         b.overflow = P<int>(h->d_flag) + 1;
+        b.fix = P<int2>(h->d_fix);
+        b.nfix = P<int>(h->d_flag) + 2;
+        b.vol = P<double>(h->d_vol);
+        b.inv_vst = (float)h->inv_vst;
         b.npmax = 2 * (int)h->runs.size();
         b.uniform = h->uniform;
         b.e0f = (float)h->edges[0];
@@ -660,10 +677,21 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         t_begin(h, 1, t);
         HIPCHK(launch_pair_bin(b, h->stream));
         t_end(h, t);
-        int flag = 0;
-        HIPCHK(hipMemcpyAsync(&flag, P<int>(h->d_flag) + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        int flag[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(flag, P<int>(h->d_flag) + 1, sizeof(flag), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        if (!flag) break;
+        if (!flag[0] && flag[1] > 0) {
+            // primaries whose predicted bin regions overflowed: exact counts
+            b.nfix_items = flag[1];
+            h->nfix_total += flag[1];
+            Timer tf;
+            t_begin(h, 1, tf);
+            HIPCHK(launch_pair_fix(b, h->stream));
+            t_end(h, tf);
+            HIPCHK(hipMemcpyAsync(flag, P<int>(h->d_flag) + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+        if (!flag[0]) break;
         if (attempt == 5) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
         unsigned long long ncap = std::min<unsigned long long>(4000000000ull, h->list_cap * 2);
         if (ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
@@ -892,7 +920,7 @@ void tpcf_destroy(tpcf_handle h) {
     DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_runs, &h->d_shift_f, &h->d_goff,
                      &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
                      &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
-                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_lcursor, &h->d_boff,
+                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag};
     for (DevBuf* b : all) release(h, *b);
@@ -1041,6 +1069,13 @@ tpcf_status tpcf_sync(tpcf_handle h) {
     if (!alive(h)) return TPCF_ERR_ARG;
     HIPCHK(hipSetDevice(h->device));
     HIPCHK(hipStreamSynchronize(h->stream));
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_rebinned_count(tpcf_handle h, int64_t* h_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!h_out) return fail(h, TPCF_ERR_ARG, "h_out is NULL");
+    *h_out = h->nfix_total;
     return TPCF_OK;
 }
 

@@ -71,7 +71,7 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
 // Pair pass (tpcf_pairs.hip)
 struct BinArgs {
     const float4* pf;        // sorted (xr, yr, zr, iz) cell-relative FP32
-    const float* pw;         // sorted FP32 weights
+    const float* pw;         // sorted FP32 weights (null: all weights are 1)
     const double4* pd;       // sorted (x, y, z, w) FP64 wrapped
     const int* catid;        // sorted catalogue id
     const int* cell_start;   // [ncat*ncell+1]
@@ -91,6 +91,11 @@ struct BinArgs {
     uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists
     uint32_t* cnt;           // [(p_end-p_begin)*nb] lengths
     int* overflow;           // [1] set when `list` is too small
+    int2* fix;               // fix-up list: (cell, chunk-relative primary) whose predicted bin regions overflowed
+    int* nfix;               // [1] its length
+    int64_t nfix_items;      // length of the list processed by a fix-up launch
+    const double* vol;       // [nb] shell volumes
+    float inv_vst;           // 1 / stencil volume (the box in one-cell mode)
     int npmax;               // capacity of the piece table (>= 2 nruns)
     int uniform;             // bins equally spaced in r: bin = floor((r - e0) / dr)
     float e0f, inv_dr;       // FP32 first edge and 1 / bin width (uniform bins)
@@ -102,6 +107,7 @@ struct BinArgs {
 };
 constexpr int kSlots = 256;  // list allocation cursors (each on its own 128-byte line)
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);
+hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s);
 size_t pair_bin_lds_bytes(int npmax);
 
 struct AlmArgs {

@@ -60,6 +60,7 @@ struct BinTables {
     double e2[kMaxBins + 1];
     float e2f[kMaxBins + 1];
     float guard[kMaxBins + 1];
+    uint32_t capoff[kMaxBins + 1];  // list layout of a primary: bin b at [capoff[b], capoff[b+1])
 };
 
 // Candidate table of a home cell in LDS. Pieces are runs of consecutive cells
@@ -224,17 +225,6 @@ __device__ void build_pieces(Pieces& W, const BinArgs& a, int cat, int cx, int c
     wave_sync();
 }
 
-// Last piece r with pref[r] <= g (pieces may be empty), branch-free.
-__device__ __forceinline__ int find_piece(const int* pref, int np, int g) {
-    int r = 0;
-#pragma unroll
-    for (int step = 128; step > 0; step >>= 1) {
-        const int c = r + step;
-        r = (c < np && pref[c] <= g) ? c : r;
-    }
-    return r;
-}
-
 // Wrap signs (+1, 2 bits per axis) of stencil offset `code` seen from cell
 // (cx, cy, cz): -1 where the neighbour cell index wrapped below 0, +1 above nc-1.
 __device__ inline int wrap_bits_of(int code, int cx, int cy, int cz, int k, int nc) {
@@ -266,6 +256,7 @@ static_assert(kGM * kNW == kItemPrims, "item size");
 // A candidate being staged: the point (cell-relative FP32), its piece's shift
 // and its index, held in registers while the previous tile is tested.
 struct Staged {
+    int r;      // piece of the slot's last candidate (advances monotonically)
     float4 q;
     float w;
     float sx, sy, zo;
@@ -279,7 +270,9 @@ __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, 
                                            const float4* pf, const float* pw) {
     st.ok = g < total;
     if (st.ok) {
-        const int r = find_piece(S.pref, np, g);
+        int r = st.r;
+        while (S.pref[r + 1] <= g) ++r;
+        st.r = r;
         const float4 rc = S.rec[r];
         st.j = (uint32_t)(g + __float_as_int(rc.x));
         st.sx = rc.y;
@@ -287,7 +280,7 @@ __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, 
         st.zo = rc.w;
         st.code = S.code[r] & 0xffff;
         st.q = pf[st.j];
-        st.w = REC ? pw[st.j] : 0.f;
+        st.w = REC ? (pw ? pw[st.j] : 1.f) : 0.f;
     }
 }
 
@@ -320,7 +313,8 @@ struct ItemCtx {
     float4* tiles;          // [2][kTile] candidates (x, y, z, w) in the home cell's frame
     uint32_t* tent;         // [2][kTile] their list entries
     const BinTables* T;
-    uint32_t* cnt;          // this wavefront's [kGM][kMaxBins] counters / offsets
+    uint32_t* cnt;          // this wavefront's [kGM][kMaxBins] counters / write cursors
+    const uint32_t* capoff; // bin regions of a primary's allocation (predicted capacities)
     int np, total;
     int64_t cs, cstart;     // first primary of this wavefront's group, catalogue start
     uint32_t cst, mask;
@@ -329,8 +323,10 @@ struct ItemCtx {
 
 // One sweep over the item's candidates. SWEEP 0 counts the hits of every
 // (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
-// bin), the offsets having been prepared in cnt: as a list entry, or with REC
-// as the record (dx, dy, dz, w_j) that the FP32 harmonic pass streams.
+// bin), the offsets having been prepared in cnt; SWEEP 2 does the same inside
+// the predicted bin regions capoff, and drops (but still counts) the hits
+// beyond a region's end. A hit is written as a list entry, or with REC as the
+// record (dx, dy, dz, w_j) that the FP32 harmonic pass streams.
 template <int SWEEP, bool SINGLE, bool UNIFORM, bool REC>
 __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, const float (&px)[kGM],
                                           const float (&py)[kGM], const float (&pz)[kGM],
@@ -343,6 +339,7 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
     Staged st[kStage];
 #pragma unroll
     for (int s = 0; s < kStage; ++s) {
+        st[s].r = 0;
         const int i = s * 64 * kNW + threadIdx.x;
         stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, i, a.pf, a.pw);
         stage_store<SINGLE>(st[s], c.tiles + i, c.tent + i, c.cst, c.cshift, a.g.hf);
@@ -406,6 +403,7 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
                     // the LDS unit serves the lanes of one atomic in a fixed
                     // order, so the lists are the same on every run
                     const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
+                    if (SWEEP == 2 && pos >= c.capoff[b + 1]) continue;
                     if constexpr (REC) {
                         a.rec[base[g] + pos] = make_float4(dx, dy, dz, q.w);
                     } else {
@@ -426,15 +424,66 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
     }
 }
 
-// Binning of the pairs of a work item (up to kItemPrims primaries of one home
-// cell) in two sweeps over the cell's candidates. Sweep 0 counts the hits of
-// every (primary, bin) with LDS atomics; the counts give each primary one
-// allocation in the list, laid out bin by bin. Sweep 1 repeats the same tests
-// and writes each hit to its final place, so no hit is buffered. Candidates
-// are staged in LDS once per tile for the whole workgroup, in the home cell's
-// frame, and every wavefront tests them against its primaries (kGM at most),
-// double-buffered so that the loads of the next tile overlap the tests.
-template <bool SINGLE, bool UNIFORM, bool REC>
+// Exact layout: counts of sweep 0 -> one allocation per wavefront; cnt
+// becomes the offset of each bin inside its primary's allocation, and
+// (offset, count) of every (p, b) is published.
+__device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]) {
+    const int lane = c.lane;
+    uint32_t tot[kGM], cl[kGM], ex[kGM];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int g = 0; g < kGM; ++g) {
+        tot[g] = cl[g] = ex[g] = 0;
+        if (g >= c.ng) continue;
+        const int cv = lane < a.nb ? (int)c.cnt[g * kMaxBins + lane] : 0;
+        int incl = cv;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        tot[g] = (uint32_t)__shfl(incl, 63, 64);
+        cl[g] = (uint32_t)cv;
+        ex[g] = (uint32_t)(incl - cv);
+        if (lane < a.nb) c.cnt[g * kMaxBins + lane] = ex[g];
+        sum += tot[g];
+    }
+    if (c.ng == 0) return;
+    const int64_t pl0 = c.cs + c.wave - a.p_begin;
+    const int slot = (int)(pl0 % kSlots);
+    const unsigned long long region = a.capacity / kSlots;
+    unsigned long long b0 = 0;
+    if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
+    b0 = __shfl(b0, 0, 64);
+    const bool ok = b0 + sum <= region;
+    if (!ok && lane == 0) atomicOr(a.overflow, 1);
+    uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
+#pragma unroll
+    for (int g = 0; g < kGM; ++g) {
+        if (g >= c.ng) continue;
+        const int64_t pl = c.cs + c.wave + kNW * g - a.p_begin;
+        if (lane < a.nb) {
+            a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
+            a.boff[pl * a.nb + lane] = ok ? run + ex[g] : 0u;
+        }
+        if (ok) base[g] = run;
+        run += tot[g];
+    }
+}
+
+// Binning of the pairs of a work item: up to kItemPrims primaries of one home
+// cell (FIX = false), or one primary of the fix-up list (FIX = true).
+// Candidates are staged in LDS once per tile for the whole workgroup, in the
+// home cell's frame, and every wavefront tests them against its primaries
+// (kGM at most), double-buffered so that the loads of the next tile overlap
+// the tests.
+//   FIX = false: one sweep. The primaries of an item share the stencil, whose
+//     candidate count measures the local density; with the shell volumes it
+//     predicts each bin's count, and a margin of 1.15x + 4 sigma + 8 gives its
+//     region in the primary's allocation. Every hit is written in place; a
+//     primary with more hits in some bin than its region holds is appended to
+//     the fix-up list instead of being published.
+//   FIX = true: two sweeps with exact counts (count, allocate, write).
+template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
 __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     extern __shared__ unsigned char smem[];
     BinTables& T = *reinterpret_cast<BinTables*>(smem);
@@ -458,13 +507,26 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     c.S = &S;
     c.tiles = tiles;
     c.tent = tent;
+    c.capoff = T.capoff;
 
-    const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
-    if (item >= a.item_hi) return;
-    const int gc = a.item_cell[item];
-    const int64_t first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
+    int gc;
+    int64_t first, last;
+    if constexpr (FIX) {
+        const int64_t item = xcd_block(blockIdx.x, (int64_t)gridDim.x);
+        if (item >= a.nfix_items) return;
+        const int2 f = a.fix[item];
+        gc = f.x;
+        first = a.p_begin + f.y;
+        last = first + 1;
+    } else {
+        const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
+        if (item >= a.item_hi) return;
+        gc = a.item_cell[item];
+        first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
+        last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
+    }
     c.cs = max(first, a.p_begin);
-    const int64_t ce = min(min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]), a.p_end);
+    const int64_t ce = min(last, a.p_end);
     if (c.cs >= ce) return;
     const int cat = gc / a.g.ncell;
     const int loc = gc - cat * a.g.ncell;
@@ -479,6 +541,7 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     __syncthreads();
     c.np = *S.n;
     c.total = S.pref[c.np];
+    const int lane = c.lane;
 
     // this wavefront's primaries: cs + wave + kNW g, g < ng
     const int rem = (int)(ce - c.cs);
@@ -496,58 +559,76 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
             pz[g] = P.z;
         }
     }
-    for (int i = c.lane; i < kGM * kMaxBins; i += 64) c.cnt[i] = 0u;
-    wave_sync();
 
-    bin_sweep<0, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
-
-    // counts -> one allocation per wavefront; cnt becomes the offset of each
-    // bin inside its primary's allocation
-    wave_sync();
-    const int lane = c.lane;
-    uint32_t tot[kGM], cl[kGM], ex[kGM];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int g = 0; g < kGM; ++g) {
-        tot[g] = cl[g] = ex[g] = 0;
-        if (g >= c.ng) continue;
-        const int cv = lane < a.nb ? (int)c.cnt[g * kMaxBins + lane] : 0;
-        int incl = cv;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += v;
+    if constexpr (FIX) {
+        for (int i = lane; i < kGM * kMaxBins; i += 64) c.cnt[i] = 0u;
+        wave_sync();
+        bin_sweep<0, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
+        wave_sync();
+        exact_layout(a, c, base);
+        wave_sync();
+        bin_sweep<1, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
+        return;
+    } else {
+        // predicted regions, the same for every primary of the item
+        if (c.wave == 0) {
+            int cap = 0;
+            if (lane < a.nb) {
+                const float pred = (float)c.total * (float)a.vol[lane] * a.inv_vst;
+                cap = (int)ceilf(1.15f * pred + 4.0f * sqrtf(pred) + 8.0f);
+            }
+            int incl = cap;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            if (lane <= a.nb) T.capoff[lane] = (uint32_t)(incl - cap);
         }
-        tot[g] = (uint32_t)__shfl(incl, 63, 64);
-        cl[g] = (uint32_t)cv;
-        ex[g] = (uint32_t)(incl - cv);
-        if (lane < a.nb) c.cnt[g * kMaxBins + lane] = ex[g];
-        sum += tot[g];
-    }
-    if (c.ng > 0) {
-        const int64_t pl0 = c.cs + c.wave - a.p_begin;
-        const int slot = (int)(pl0 % kSlots);
-        const unsigned long long region = a.capacity / kSlots;
-        unsigned long long b0 = 0;
-        if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
-        b0 = __shfl(b0, 0, 64);
-        const bool ok = b0 + sum <= region;
-        if (!ok && lane == 0) atomicOr(a.overflow, 1);
-        uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
+        __syncthreads();
+        const uint32_t captot = T.capoff[a.nb];
+        for (int i = lane; i < kGM * kMaxBins; i += 64)
+            c.cnt[i] = (i % kMaxBins) < a.nb ? T.capoff[i % kMaxBins] : 0u;
+        bool ok = true;
+        if (c.ng > 0) {
+            const unsigned long long sum = (unsigned long long)captot * (unsigned)c.ng;
+            const int64_t pl0 = c.cs + c.wave - a.p_begin;
+            const int slot = (int)(pl0 % kSlots);
+            const unsigned long long region = a.capacity / kSlots;
+            unsigned long long b0 = 0;
+            if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, sum);
+            b0 = __shfl(b0, 0, 64);
+            ok = b0 + sum <= region;
+            if (!ok && lane == 0) atomicOr(a.overflow, 1);
+            const uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
+#pragma unroll
+            for (int g = 0; g < kGM; ++g)
+                if (ok && g < c.ng) base[g] = run + (uint32_t)g * captot;
+        }
+        wave_sync();
+        bin_sweep<2, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
+        wave_sync();
 #pragma unroll
         for (int g = 0; g < kGM; ++g) {
             if (g >= c.ng) continue;
             const int64_t pl = c.cs + c.wave + kNW * g - a.p_begin;
+            uint32_t cv = 0, cap = 0, co = 0;
             if (lane < a.nb) {
-                a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
-                a.boff[pl * a.nb + lane] = ok ? run + ex[g] : 0u;
+                co = T.capoff[lane];
+                cap = T.capoff[lane + 1] - co;
+                cv = c.cnt[g * kMaxBins + lane] - co;
             }
-            if (ok) base[g] = run;
-            run += tot[g];
+            const bool over = __ballot(lane < a.nb && cv > cap) != 0;
+            if (over && ok && lane == 0) {
+                const int k = atomicAdd(a.nfix, 1);
+                a.fix[k] = make_int2(gc, (int)pl);
+            }
+            if (lane < a.nb) {
+                const bool pub = ok && !over;
+                a.cnt[pl * a.nb + lane] = pub ? cv : 0u;
+                a.boff[pl * a.nb + lane] = pub ? base[g] + co : 0u;
+            }
         }
     }
-    wave_sync();
-
-    bin_sweep<1, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
 }
 
 // ---------------------------------------------------------------- harmonics
@@ -764,26 +845,26 @@ hipError_t launch_alm_lmax(const AlmArgs& a, int fp64, hipStream_t s) {
 
 }  // namespace
 
-template <bool SINGLE, bool UNIFORM, bool REC>
+template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
 hipError_t launch_bin_variant(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void*)k_pair_bin<SINGLE, UNIFORM, REC>,
+        hipFuncSetAttribute((const void*)k_pair_bin<SINGLE, UNIFORM, REC, FIX>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_pair_bin<SINGLE, UNIFORM, REC>), dim3((unsigned)nblk), dim3(64 * kNW), lds, s, a);
+    hipLaunchKernelGGL((k_pair_bin<SINGLE, UNIFORM, REC, FIX>), dim3((unsigned)nblk), dim3(64 * kNW), lds, s, a);
     return hipGetLastError();
 }
 
-template <bool REC>
+template <bool REC, bool FIX>
 hipError_t launch_bin_rec(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
     if (a.g.single) {
-        return a.uniform ? launch_bin_variant<true, true, REC>(a, s, nblk, lds)
-                         : launch_bin_variant<true, false, REC>(a, s, nblk, lds);
+        return a.uniform ? launch_bin_variant<true, true, REC, FIX>(a, s, nblk, lds)
+                         : launch_bin_variant<true, false, REC, FIX>(a, s, nblk, lds);
     }
-    return a.uniform ? launch_bin_variant<false, true, REC>(a, s, nblk, lds)
-                     : launch_bin_variant<false, false, REC>(a, s, nblk, lds);
+    return a.uniform ? launch_bin_variant<false, true, REC, FIX>(a, s, nblk, lds)
+                     : launch_bin_variant<false, false, REC, FIX>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
@@ -792,7 +873,14 @@ hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
     // a multiple of 8 blocks, so that the XCD remap is a permutation
     const int64_t nblk = (nitems + 7) / 8 * 8;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
-    return a.rec ? launch_bin_rec<true>(a, s, nblk, lds) : launch_bin_rec<false>(a, s, nblk, lds);
+    return a.rec ? launch_bin_rec<true, false>(a, s, nblk, lds) : launch_bin_rec<false, false>(a, s, nblk, lds);
+}
+
+hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s) {
+    if (a.p_end <= a.p_begin || a.nfix_items <= 0) return hipSuccess;
+    const int64_t nblk = (a.nfix_items + 7) / 8 * 8;
+    const size_t lds = pair_bin_lds_bytes(a.npmax);
+    return a.rec ? launch_bin_rec<true, true>(a, s, nblk, lds) : launch_bin_rec<false, true>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {

@@ -33,7 +33,7 @@ F_PAPER_LITERAL = 2
 
 EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
-           "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_set_timing",
+           "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
            "tpcf_stage_times"]
 
 
@@ -85,6 +85,8 @@ def load():
     lib.tpcf_sync.restype = st
     lib.tpcf_pair_count.argtypes = [vp, ctypes.POINTER(i64)]
     lib.tpcf_pair_count.restype = st
+    lib.tpcf_rebinned_count.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.tpcf_rebinned_count.restype = st
     lib.tpcf_set_timing.argtypes = [vp, ctypes.c_int]
     lib.tpcf_set_timing.restype = st
     lib.tpcf_stage_times.argtypes = [vp, i32, vp, vp]
@@ -216,6 +218,11 @@ class Handle:
     def pair_count(self):
         v = ctypes.c_int64(0)
         self._chk(self.lib.tpcf_pair_count(self.h, ctypes.byref(v)))
+        return int(v.value)
+
+    def rebinned_count(self):
+        v = ctypes.c_int64(0)
+        self._chk(self.lib.tpcf_rebinned_count(self.h, ctypes.byref(v)))
         return int(v.value)
 
     def set_timing(self, enable=True):

@@ -85,6 +85,7 @@ def test_null_arguments(lib):
     assert lib.tpcf_build_grid(None, None, None, 10, 10) == T.TPCF_ERR_ARG
     assert lib.tpcf_alm_accumulate(None) == T.TPCF_ERR_ARG
     assert lib.tpcf_sync(None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_rebinned_count(None, None) == T.TPCF_ERR_ARG
     assert b"invalid" in lib.tpcf_last_error(None)
     lib.tpcf_destroy(None)
 

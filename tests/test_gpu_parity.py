@@ -231,6 +231,31 @@ def test_batched_equals_single_bitwise(torch, prec):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
+def test_crowded_cluster_exact_rebinning(torch, prec):
+    """A dense clump inside a sparse box: its members see far more close
+    neighbours than their cell's stencil predicts, so they take the exact
+    rebinning path; the result must still match the oracle."""
+    box, edges, lmax = 120.0, np.linspace(2.0, 30.0, 8), 4
+    rng = np.random.default_rng(C.catalogue_seed(9))
+    clump = 40.0 + rng.normal(0.0, 1.5, size=(600, 3))
+    pos = np.vstack([C.poisson(1400, box, C.catalogue_seed(8)), np.mod(clump, box)])
+    mults = O.all_multipoles(lmax, 2)
+    ref, _, res = O.run(pos, box, edges, lmax, mults)
+    h = T.Handle(box, edges, lmax, precision=prec)
+    h.build_grid(gpu(torch, pos))
+    h.alm_accumulate()
+    h.contract()
+    out = h.multipoles(mults)
+    h.sync()
+    npairs, nfix = h.pair_count(), h.rebinned_count()
+    h.close()
+    say(f"  crowded {PNAME[prec]}: rebinned primaries {nfix}")
+    assert nfix > 0
+    assert npairs == res.npairs
+    assert rel_err(out.cpu().numpy(), ref) < TOL[prec]
+
+
 def test_nonfinite_positions_reported(torch):
     pos = C.poisson(500, 50.0, 141)
     pos[17, 1] = np.nan
