@@ -78,14 +78,14 @@ struct tpcf_handle_s {
     std::vector<double> n_data;
     bool unit_w = true;
     DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
-        d_catid, d_flag, d_istart, d_icell, d_icat;
+        d_catid, d_flag, d_istart, d_icell, d_icat, d_scanw;
     std::vector<int> item_cat;       // [ncat+1] first work item of each catalogue
 
     // pair pass
     std::vector<int64_t> sub_start;  // global subchunks (sorted index of first primary), + end
     std::vector<int> cat_sub;        // [ncat+1]
     std::vector<Chunk> chunks;
-    int64_t kc = 4096;
+    int64_t kc = 4096;  // primaries per subchunk (the self-moment kernel stages at most 4096 weights)
     int uniform = 0;      // bins equally spaced in r
     float inv_dr = 0.f;   // 1 / bin width (uniform bins)
     float delta = 0.f;    // FP32 guard band in units of the bin width
@@ -506,6 +506,7 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_cellid, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_count, sizeof(int) * (M + 1))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_start, sizeof(int) * (M + 1))) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_scanw, sizeof(int) * grid_scan_work_ints(M))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_cursor, sizeof(int) * (M + 1))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_tmp, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_orig, sizeof(int) * N)) != TPCF_OK) return st;
@@ -523,7 +524,7 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     HIPCHK(launch_fill_i32(P<int>(h->d_flag), 4, 0, h->stream));
     HIPCHK(launch_grid_assign(d_pos, d_w, N, P<int64_t>(h->d_pt_off), h->ncat, h->g, P<int>(h->d_cellid),
                               P<int>(h->d_count), P<int>(h->d_flag), h->stream));
-    HIPCHK(launch_grid_scan(P<int>(h->d_count), M, P<int>(h->d_start), h->stream));
+    HIPCHK(launch_grid_scan(P<int>(h->d_count), M, P<int>(h->d_start), P<int>(h->d_scanw), h->stream));
     HIPCHK(launch_grid_scatter(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_cursor),
                                P<int>(h->d_tmp), h->stream));
     HIPCHK(launch_grid_order(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_tmp),
@@ -537,7 +538,7 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_icell, sizeof(int) * nitems_max)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_icat, sizeof(int) * (h->ncat + 1))) != TPCF_OK) return st;
     HIPCHK(launch_items_count(P<int>(h->d_start), M, P<int>(h->d_cursor), h->stream));
-    HIPCHK(launch_grid_scan(P<int>(h->d_cursor), M, P<int>(h->d_istart), h->stream));
+    HIPCHK(launch_grid_scan(P<int>(h->d_cursor), M, P<int>(h->d_istart), P<int>(h->d_scanw), h->stream));
     HIPCHK(launch_items_fill(P<int>(h->d_istart), M, P<int>(h->d_icell), h->stream));
     HIPCHK(launch_items_cat(P<int>(h->d_istart), h->ncat, h->g.ncell, P<int>(h->d_icat), h->stream));
     t_end(h, t);
@@ -920,7 +921,7 @@ void tpcf_destroy(tpcf_handle h) {
     DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_runs, &h->d_shift_f, &h->d_goff,
                      &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
                      &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
-                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
+                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_scanw, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag};
     for (DevBuf* b : all) release(h, *b);

@@ -465,8 +465,14 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
 }
 
 // Degenerate-triangle moments sum_p w_p sum_j w_j^2 R^0_L(z_pj) and pair
-// counts per bin, one workgroup per subchunk, one wavefront per task.
+// counts per bin. One workgroup per (subchunk, group of kSelfTasks tasks); the
+// subchunk's primary weights are staged in LDS once, and every wavefront sums
+// its tasks with four independent FP64 partial sums in a fixed order.
+constexpr int kSelfTasks = 16;
+constexpr int kSelfMaxSub = 4096;  // primaries per subchunk
+
 __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
+    __shared__ double wsh[kSelfMaxSub];
     const int s = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nL = 2 * a.lmax + 1;
@@ -475,19 +481,37 @@ __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
     const int NV = n_values(a.lmax);
     const int na = n_alm_values(a.lmax);
     const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
-    for (int task = wave; task < ntask; task += 4) {
+    const int n = (int)(pb - pa);
+    for (int i = threadIdx.x; i < n; i += 256) wsh[i] = a.pd[a.p_begin + pa + i].w;
+    __syncthreads();
+    for (int q = 0; q < kSelfTasks / 4; ++q) {
+        const int task = blockIdx.y * kSelfTasks + wave * (kSelfTasks / 4) + q;
+        if (task >= ntask) break;
         const int b = task / width, L = task - b * width;
-        double sum = 0.0;
-        for (int64_t p = pa + lane; p < pb; p += 64) {
-            if (L < nL) {
-                const int64_t idx = ((int64_t)b * NV + na + L) * a.ldA + p;
-                const double v = a.fp64 ? reinterpret_cast<const double*>(a.A)[idx]
-                                        : (double)reinterpret_cast<const float*>(a.A)[idx];
-                sum += a.pd[a.p_begin + p].w * v;
-            } else {
-                sum += (double)a.cnt[p * a.nb + b];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (L < nL) {
+            const int64_t row = ((int64_t)b * NV + na + L) * a.ldA + pa;
+            for (int p0 = 0; p0 < n; p0 += 256) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int p = p0 + 64 * u + lane;
+                    if (p < n) {
+                        const double v = a.fp64 ? reinterpret_cast<const double*>(a.A)[row + p]
+                                                : (double)reinterpret_cast<const float*>(a.A)[row + p];
+                        acc[u] += wsh[p] * v;
+                    }
+                }
+            }
+        } else {
+            for (int p0 = 0; p0 < n; p0 += 256) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int p = p0 + 64 * u + lane;
+                    if (p < n) acc[u] += (double)a.cnt[(pa + p) * a.nb + b];
+                }
             }
         }
+        double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
         if (lane == 0) a.part[(int64_t)(a.sub_base + s) * a.nb * width + task] = sum;
     }
@@ -679,7 +703,9 @@ size_t contract_lds_bytes(int mode, int nb, int lmax) {
 
 hipError_t launch_self_moments(const SelfArgs& a, hipStream_t s) {
     if (a.nsub <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_self_moments, dim3(a.nsub), dim3(256), 0, s, a);
+    const int ntask = a.nb * (2 * a.lmax + 2);
+    hipLaunchKernelGGL(k_self_moments, dim3(a.nsub, (ntask + kSelfTasks - 1) / kSelfTasks), dim3(256), 0, s,
+                       a);
     return hipGetLastError();
 }
 

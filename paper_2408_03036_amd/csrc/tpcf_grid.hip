@@ -79,6 +79,61 @@ __global__ void __launch_bounds__(1024) k_grid_scan(const int* __restrict__ coun
     if (t == 1023) start[m] = part[1023];
 }
 
+// Three-phase exclusive scan of m counts: per-block sums of kScanBlock
+// elements, a scan of the block sums (k_grid_scan), then each block's scan
+// plus its offset.
+constexpr int kScanBlock = 4096;  // 256 threads x 16 elements
+
+__global__ void __launch_bounds__(256) k_scan_sums(const int* __restrict__ count, int64_t m,
+                                                   int* __restrict__ sums) {
+    __shared__ int red[256];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    int s = 0;
+    for (int i = threadIdx.x; i < kScanBlock; i += 256) {
+        const int64_t e = b0 + i;
+        if (e < m) s += count[e];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ count, int64_t m,
+                                                    const int* __restrict__ boff, int* __restrict__ start) {
+    __shared__ int part[256];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    const int t = threadIdx.x;
+    // thread t owns elements [b0 + 16 t, b0 + 16 t + 16)
+    int v[16];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int64_t e = b0 + 16 * t + k;
+        v[k] = e < m ? count[e] : 0;
+        s += v[k];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int x = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    int run = boff[blockIdx.x] + part[t] - s;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int64_t e = b0 + 16 * t + k;
+        if (e < m) start[e] = run;
+        if (e == m - 1) start[m] = run + v[k];
+        run += v[k];
+    }
+}
+
 __global__ void k_grid_scatter(const int* __restrict__ cellid, int64_t n,
                                const int* __restrict__ start, int* __restrict__ cursor,
                                int* __restrict__ tmp_idx) {
@@ -196,10 +251,20 @@ hipError_t launch_grid_assign(const double* pos, const double*, int64_t n, const
     return hipGetLastError();
 }
 
-hipError_t launch_grid_scan(const int* count, int64_t m, int* start, hipStream_t s) {
-    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, count, m, start);
+hipError_t launch_grid_scan(const int* count, int64_t m, int* start, int* work, hipStream_t s) {
+    const int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+    if (nb <= 1) {
+        hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, count, m, start);
+        return hipGetLastError();
+    }
+    // work: nb block sums, then nb + 1 block offsets
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, count, m, work);
+    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, work, nb, work + nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, count, m, work + nb, start);
     return hipGetLastError();
 }
+
+int64_t grid_scan_work_ints(int64_t m) { return 2 * ((m + kScanBlock - 1) / kScanBlock) + 1; }
 
 hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, int* cursor,
                                int* tmp_idx, hipStream_t s) {

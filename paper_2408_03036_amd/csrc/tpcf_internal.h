@@ -52,7 +52,9 @@ struct CatArrays {
 hipError_t launch_grid_assign(const double* pos, const double* w, int64_t n, const int64_t* pt_off,
                               int ncat, Grid g, int* cellid, int* count, int* nonfinite,
                               hipStream_t s);
-hipError_t launch_grid_scan(const int* count, int64_t m, int* start, hipStream_t s);
+// Exclusive scan of m counts into start[0..m]; work holds grid_scan_work_ints(m) ints.
+hipError_t launch_grid_scan(const int* count, int64_t m, int* start, int* work, hipStream_t s);
+int64_t grid_scan_work_ints(int64_t m);
 hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, int* cursor,
                                int* tmp_idx, hipStream_t s);
 hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, const int* tmp_idx,
