@@ -42,6 +42,7 @@ struct Timer {
 struct Chunk {
     int64_t p_begin, p_end;  // sorted indices
     int sub_begin, sub_end;  // global subchunk range
+    int sub_off;             // offset of the chunk's relative subchunk table in d_subs
 };
 
 }  // namespace
@@ -612,8 +613,14 @@ tpcf_status plan_chunks(tpcf_handle h) {
     if ((st = ensure(h, h->d_A, (size_t)h->nb * h->NV * h->ldA * elem)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_lcursor, sizeof(unsigned long long) * kSlots * 16)) != TPCF_OK) return st;
-    // subchunk tables: per chunk, chunk-relative starts are uploaded on demand
-    if ((st = ensure(h, h->d_subs, sizeof(int) * (nsub + 1) + 64)) != TPCF_OK) return st;
+    // subchunk tables: chunk-relative starts of every chunk, one upload
+    std::vector<int> rel;
+    for (Chunk& ch : h->chunks) {
+        ch.sub_off = (int)rel.size();
+        for (int q = ch.sub_begin; q <= ch.sub_end; ++q) rel.push_back((int)(h->sub_start[q] - ch.p_begin));
+    }
+    if ((st = ensure(h, h->d_subs, sizeof(int) * rel.size() + 64)) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_subs, rel.data(), sizeof(int) * rel.size())) != TPCF_OK) return st;
     if ((st = upload(h, h->d_catsub, h->cat_sub.data(), sizeof(int) * (h->ncat + 1))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_part, (size_t)nsub * h->gsize * sizeof(double))) != TPCF_OK) return st;
     const int sw = h->nb * (2 * h->lmax + 2);
@@ -622,11 +629,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
 }
 
 tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
-    std::vector<int> rel(ch.sub_end - ch.sub_begin + 1);
-    for (int s = ch.sub_begin; s <= ch.sub_end; ++s) rel[s - ch.sub_begin] = (int)(h->sub_start[s] - ch.p_begin);
     tpcf_status st;
-    // the table is chunk-specific; the copy is stream-ordered before its use
-    if ((st = upload(h, h->d_subs, rel.data(), sizeof(int) * rel.size())) != TPCF_OK) return st;
     for (int attempt = 0; attempt < 6; ++attempt) {
         HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), kSlots * 16, 0ull, h->stream));
         HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 2, 0, h->stream));  // overflow, fix-up count
@@ -736,7 +739,7 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     c.p_begin = ch.p_begin;
     c.nb = h->nb;
     c.lmax = h->lmax;
-    c.sub_start = P<int>(h->d_subs);
+    c.sub_start = P<int>(h->d_subs) + ch.sub_off;
     c.nsub = nsub;
     c.sub_base = ch.sub_begin;
     c.part32 = nullptr;
@@ -755,7 +758,7 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     s.p_begin = ch.p_begin;
     s.nb = h->nb;
     s.lmax = h->lmax;
-    s.sub_start = P<int>(h->d_subs);
+    s.sub_start = P<int>(h->d_subs) + ch.sub_off;
     s.nsub = nsub;
     s.sub_base = ch.sub_begin;
     s.part = P<double>(h->d_pself);

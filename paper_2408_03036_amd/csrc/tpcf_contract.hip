@@ -275,12 +275,13 @@ __device__ inline void split8(float (&x)[8], uint4 (&out)[NPC]) {
     }
 }
 
+template <bool W>
 struct BfStage {
     float x[kBfIPT][8];
-    float w[kBfIPT][8];
+    float w[W ? kBfIPT : 1][8];
 };
 
-template <int NPC>
+template <int NPC, bool W>
 __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a, int KS, int nbuf) {
     constexpr int TS = 32;
     extern __shared__ unsigned char smem[];
@@ -301,7 +302,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
     const int ncol = nt * TS;
     const int KSP = KS + 8;
-    const bool weighted = !a.unit_weights;
+    constexpr bool weighted = W;
     const int nplanes = weighted ? 2 * NPC : NPC;
     const int plane = ncol * KSP;                 // elements per plane
     const int bufsz = nplanes * plane;            // elements per buffer
@@ -330,24 +331,40 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     const int nkst = (int)((pb - pa + KS - 1) / KS);
     const int nsteps = nkst * parts;
 
+    // The thread's staging items do not change from step to step: column c
+    // and primaries k8..k8+7 of the step. Their A row (part 0), LDS offset and
+    // validity are computed once.
+    int64_t irow[kBfIPT];
+    int ioff[kBfIPT], ik8[kBfIPT];
+    bool iok[kBfIPT], istore[kBfIPT];
+#pragma unroll
+    for (int u = 0; u < kBfIPT; ++u) {
+        const int it = threadIdx.x + u * 64 * kBfWaves;
+        const int c = it / groups, k8 = (it - c * groups) * 8;
+        const int b = c / nl, lp = c - b * nl;
+        istore[u] = it < nitems;
+        iok[u] = it < nitems && c < K;
+        ik8[u] = k8;
+        ioff[u] = c * KSP + k8;
+        irow[u] = ((int64_t)b * NV + voff + lp) * a.ldA + k8;
+    }
+    const int64_t part_stride = (int64_t)nl * a.ldA;
+
     // loads of step st into registers
-    auto load = [&](int st, BfStage& R) {
+    auto load = [&](int st, BfStage<W>& R) {
         const int part = st % parts;
         const int64_t p0 = pa + (int64_t)(st / parts) * KS;
         const int kv = (int)min((int64_t)KS, pb - p0);
 #pragma unroll
         for (int u = 0; u < kBfIPT; ++u) {
-            const int it = threadIdx.x + u * 64 * kBfWaves;
-            const int c = it / groups, k8 = (it - c * groups) * 8;
+            const int k8 = ik8[u];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 R.x[u][e] = 0.f;
-                R.w[u][e] = 0.f;
+                if constexpr (W) R.w[u][e] = 0.f;
             }
-            if (it >= nitems || c >= K || k8 >= kv) continue;
-            const int b = c / nl, lp = c - b * nl;
-            const int64_t row = (int64_t)b * NV + voff + part * nl + lp;
-            const float* src = A + row * a.ldA + p0 + k8;
+            if (!iok[u] || k8 >= kv) continue;
+            const float* src = A + irow[u] + part * part_stride + p0;
             const float* wsrc = a.pw + a.p_begin + p0 + k8;
             if (k8 + 8 <= kv) {
                 float4 v0, v1;
@@ -355,7 +372,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
                 __builtin_memcpy(&v1, src + 4, 16);
                 R.x[u][0] = v0.x; R.x[u][1] = v0.y; R.x[u][2] = v0.z; R.x[u][3] = v0.w;
                 R.x[u][4] = v1.x; R.x[u][5] = v1.y; R.x[u][6] = v1.z; R.x[u][7] = v1.w;
-                if (weighted) {
+                if constexpr (W) {
                     __builtin_memcpy(&v0, wsrc, 16);
                     __builtin_memcpy(&v1, wsrc + 4, 16);
                     R.w[u][0] = v0.x; R.w[u][1] = v0.y; R.w[u][2] = v0.z; R.w[u][3] = v0.w;
@@ -366,23 +383,21 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
                 for (int e = 0; e < 8; ++e) {
                     if (k8 + e < kv) {
                         R.x[u][e] = src[e];
-                        if (weighted) R.w[u][e] = wsrc[e];
+                        if constexpr (W) R.w[u][e] = wsrc[e];
                     }
                 }
             }
         }
     };
     // converts the registers of a step into BF16 planes of buffer `buf`
-    auto store = [&](int buf, BfStage& R) {
+    auto store = [&](int buf, BfStage<W>& R) {
         uint16_t* base = lds + buf * bufsz;
 #pragma unroll
         for (int u = 0; u < kBfIPT; ++u) {
-            const int it = threadIdx.x + u * 64 * kBfWaves;
-            if (it >= nitems) continue;
-            const int c = it / groups, k8 = (it - c * groups) * 8;
-            const int off = c * KSP + k8;
+            if (!istore[u]) continue;
+            const int off = ioff[u];
             float y[8];
-            if (weighted) {
+            if constexpr (W) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) y[e] = R.x[u][e] * R.w[u][e];
             }
@@ -390,7 +405,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
             split8<NPC>(R.x[u], pc);
 #pragma unroll
             for (int q = 0; q < NPC; ++q) *reinterpret_cast<uint4*>(base + q * plane + off) = pc[q];
-            if (weighted) {
+            if constexpr (W) {
                 split8<NPC>(y, pc);
 #pragma unroll
                 for (int q = 0; q < NPC; ++q) *reinterpret_cast<uint4*>(base + (NPC + q) * plane + off) = pc[q];
@@ -398,15 +413,9 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
         }
     };
 
-    BfStage R;
-    load(0, R);
-    store(0, R);
-    __syncthreads();
     const int i = lane & 31, kg = lane >> 5;
-    for (int st = 0; st < nsteps; ++st) {
-        const int buf = nbuf == 2 ? (st & 1) : 0;
-        const bool more = st + 1 < nsteps;
-        if (more && nbuf == 2) load(st + 1, R);
+    // MFMAs of step st from LDS buffer buf, then the FP64 flush after the last part
+    auto compute = [&](int st, int buf) {
         const uint16_t* xp = lds + buf * bufsz;
         const uint16_t* wp = weighted ? xp + NPC * plane : xp;
         for (int k0 = 0; k0 < KS; k0 += 16) {
@@ -439,16 +448,41 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
                 acc32[q] = (f32x16)0.0f;
             }
         }
-        if (more) {
-            if (nbuf == 2) {
-                store(buf ^ 1, R);
-            } else {
+    };
+
+    if (nbuf == 2) {
+        // two LDS buffers and two register stages: the loads of step st + 2
+        // are issued before the MFMAs of step st, and step st + 1 (loaded a
+        // step earlier) is converted into the other buffer after them
+        BfStage<W> R0, R1;
+        load(0, R0);
+        store(0, R0);
+        if (nsteps > 1) load(1, R1);
+        __syncthreads();
+        auto step = [&](int st, BfStage<W>& Rload, BfStage<W>& Rstore) {
+            if (st + 2 < nsteps) load(st + 2, Rload);
+            compute(st, st & 1);
+            if (st + 1 < nsteps) store((st + 1) & 1, Rstore);
+            __syncthreads();
+        };
+        for (int st = 0; st < nsteps; st += 2) {
+            step(st, R0, R1);
+            if (st + 1 < nsteps) step(st + 1, R1, R0);
+        }
+    } else {
+        BfStage<W> R;
+        load(0, R);
+        store(0, R);
+        __syncthreads();
+        for (int st = 0; st < nsteps; ++st) {
+            compute(st, 0);
+            if (st + 1 < nsteps) {
                 __syncthreads();
                 load(st + 1, R);
                 store(0, R);
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     const int64_t sg = (int64_t)(a.sub_base + s);
 #pragma unroll
@@ -659,8 +693,8 @@ BfPlan bf_plan(int npc, int ncol, bool weighted) {
     return {0, 0, 0};
 }
 
-template <int NPC>
-hipError_t launch_contract_bf16(const ContractArgs& a, hipStream_t s) {
+template <int NPC, bool W>
+hipError_t launch_contract_bf16_w(const ContractArgs& a, hipStream_t s) {
     const int K0 = a.nb * (a.lmax + 1);
     const int nt0 = (K0 + 31) / 32;
     const int ntiles0 = nt0 * (nt0 + 1) / 2;
@@ -669,13 +703,18 @@ hipError_t launch_contract_bf16(const ContractArgs& a, hipStream_t s) {
     if (pl.KS == 0) return hipErrorInvalidValue;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void*)k_contract_bf16<NPC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipFuncSetAttribute((const void*)k_contract_bf16<NPC, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL(k_contract_bf16<NPC>, dim3(a.nsub, a.lmax + 1, ngroups), dim3(64 * kBfWaves), pl.lds,
-                       s, a, pl.KS, pl.nbuf);
+    hipLaunchKernelGGL((k_contract_bf16<NPC, W>), dim3(a.nsub, a.lmax + 1, ngroups), dim3(64 * kBfWaves),
+                       pl.lds, s, a, pl.KS, pl.nbuf);
     return hipGetLastError();
+}
+
+template <int NPC>
+hipError_t launch_contract_bf16(const ContractArgs& a, hipStream_t s) {
+    return a.unit_weights ? launch_contract_bf16_w<NPC, false>(a, s) : launch_contract_bf16_w<NPC, true>(a, s);
 }
 
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s) {
