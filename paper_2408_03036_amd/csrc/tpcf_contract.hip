@@ -248,7 +248,9 @@ __global__ void __launch_bounds__(256) k_contract(ContractArgs a) {
 // next step are in flight while the MFMAs of the current one run.
 constexpr int kBfWaves = 8;
 constexpr int kBfTPW = 2;
-constexpr int kBfIPT = 2;  // staged 8-element groups per thread and step
+// staged 8-element groups per thread and step: four without weights, two with
+// (the weighted staging also holds the weights)
+template <bool W> constexpr int bf_ipt() { return W ? 2 : 4; }
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
@@ -277,8 +279,8 @@ __device__ inline void split8(float (&x)[8], uint4 (&out)[NPC]) {
 
 template <bool W>
 struct BfStage {
-    float x[kBfIPT][8];
-    float w[W ? kBfIPT : 1][8];
+    float x[bf_ipt<W>()][8];
+    float w[W ? bf_ipt<W>() : 1][8];
 };
 
 template <int NPC, bool W>
@@ -303,6 +305,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     const int ncol = nt * TS;
     const int KSP = KS + 8;
     constexpr bool weighted = W;
+    constexpr int IPT = bf_ipt<W>();
     const int nplanes = weighted ? 2 * NPC : NPC;
     const int plane = ncol * KSP;                 // elements per plane
     const int bufsz = nplanes * plane;            // elements per buffer
@@ -334,11 +337,11 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     // The thread's staging items do not change from step to step: column c
     // and primaries k8..k8+7 of the step. Their A row (part 0), LDS offset and
     // validity are computed once.
-    int64_t irow[kBfIPT];
-    int ioff[kBfIPT], ik8[kBfIPT];
-    bool iok[kBfIPT], istore[kBfIPT];
+    int64_t irow[IPT];
+    int ioff[IPT], ik8[IPT];
+    bool iok[IPT], istore[IPT];
 #pragma unroll
-    for (int u = 0; u < kBfIPT; ++u) {
+    for (int u = 0; u < IPT; ++u) {
         const int it = threadIdx.x + u * 64 * kBfWaves;
         const int c = it / groups, k8 = (it - c * groups) * 8;
         const int b = c / nl, lp = c - b * nl;
@@ -356,7 +359,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
         const int64_t p0 = pa + (int64_t)(st / parts) * KS;
         const int kv = (int)min((int64_t)KS, pb - p0);
 #pragma unroll
-        for (int u = 0; u < kBfIPT; ++u) {
+        for (int u = 0; u < IPT; ++u) {
             const int k8 = ik8[u];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -393,7 +396,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     auto store = [&](int buf, BfStage<W>& R) {
         uint16_t* base = lds + buf * bufsz;
 #pragma unroll
-        for (int u = 0; u < kBfIPT; ++u) {
+        for (int u = 0; u < IPT; ++u) {
             if (!istore[u]) continue;
             const int off = ioff[u];
             float y[8];
@@ -684,9 +687,10 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
 struct BfPlan { int KS, nbuf; size_t lds; };
 BfPlan bf_plan(int npc, int ncol, bool weighted) {
     const int nplanes = weighted ? 2 * npc : npc;
+    const int ipt = weighted ? bf_ipt<true>() : bf_ipt<false>();
     for (int nbuf = 2; nbuf >= 1; --nbuf)
-        for (int KS = 64; KS >= 16; KS /= 2) {
-            if ((size_t)ncol * (KS / 8) > (size_t)64 * kBfWaves * kBfIPT) continue;
+        for (int KS = 128; KS >= 16; KS /= 2) {
+            if ((size_t)ncol * (KS / 8) > (size_t)64 * kBfWaves * ipt) continue;
             const size_t lds = (size_t)nbuf * nplanes * ncol * (KS + 8) * sizeof(uint16_t);
             if (lds <= 160 * 1024) return {KS, nbuf, lds};
         }

@@ -723,21 +723,20 @@ __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) 
 }
 
 template <typename T, int LMAX, int G>
-__global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
+__global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
     using AC = Acc<T, LMAX, G>;
     constexpr int NV = n_values(LMAX);
+    // One wavefront per workgroup: 64 consecutive primaries of one bin. The
+    // wavefronts of a block of 256 primaries are consecutive, bin by bin.
     const int lane = lane_id();
     const int64_t nprim = a.p_end - a.p_begin;
-    const int64_t nblk64 = (nprim + 63) / 64;
-    const int64_t nwaves = nblk64 * a.nb;
-    const int64_t nwg = (nwaves + 3) / 4;
-    const int64_t wg = xcd_block(blockIdx.x, (int64_t)gridDim.x);
-    if (wg >= nwg) return;
-    const int64_t wv = wg * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = ((nprim + 255) / 256) * a.nb * 4;
+    const int64_t wv = xcd_block(blockIdx.x, (int64_t)gridDim.x);
     if (wv >= nwaves) return;
-    const int64_t blk = wv / a.nb;
-    const int b = (int)(wv - blk * a.nb);
-    const int64_t pl = blk * 64 + lane;
+    const int64_t blk = wv / (4 * a.nb);
+    const int rem = (int)(wv - blk * 4 * a.nb);
+    const int b = rem >> 2;
+    const int64_t pl = blk * 256 + (rem & 3) * 64 + lane;
     const int64_t p = a.p_begin + pl;
     const bool active = pl < nprim;
 
@@ -813,10 +812,9 @@ __global__ void __launch_bounds__(256) k_pair_alm(AlmArgs a) {
 template <typename T, int LMAX, int G>
 hipError_t launch_alm_one(const AlmArgs& a, hipStream_t s) {
     const int64_t nprim = a.p_end - a.p_begin;
-    const int64_t nwaves = ((nprim + 63) / 64) * a.nb;
-    int64_t nwg = (nwaves + 3) / 4;
-    nwg = (nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_pair_alm<T, LMAX, G>), dim3((unsigned)nwg), dim3(256), 0, s, a);
+    const int64_t nwaves = ((nprim + 255) / 256) * a.nb * 4;
+    const int64_t nwg = (nwaves + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_pair_alm<T, LMAX, G>), dim3((unsigned)nwg), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
