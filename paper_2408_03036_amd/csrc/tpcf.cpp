@@ -715,6 +715,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     a.p_end = ch.p_end;
     a.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
     a.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
+    a.unit_w = h->unit_w ? 1 : 0;
     a.boff = P<uint32_t>(h->d_boff);
     a.cnt = P<uint32_t>(h->d_cnt);
     a.A = h->d_A.p;

@@ -124,6 +124,7 @@ struct AlmArgs {
     int64_t p_begin, p_end;
     const uint32_t* list;    // list entries (FP64 path)
     const float4* rec;       // hit records (dx, dy, dz, w_j) (FP32 paths)
+    int unit_w;              // all weights are 1
     const uint32_t* boff;
     const uint32_t* cnt;
     void* A;                 // [nb][nvalues][ldA] float or double

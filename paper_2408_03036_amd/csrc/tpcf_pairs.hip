@@ -665,33 +665,37 @@ struct Acc {
 };
 
 // Accumulates one neighbour (unit vector x,y,z; weight w).
-template <typename T, int LMAX, int G>
+// Accumulates one neighbour (unit vector x,y,z; weight w). With UNIT all
+// weights are 1: the self moments of order L <= lmax then equal the m = 0
+// coefficients and are not accumulated twice (the caller copies them).
+template <typename T, int LMAX, int G, bool UNIT>
 __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) {
     using AC = Acc<T, LMAX, G>;
     constexpr int MLO = AC::MLO, MHI = AC::MHI, V0 = AC::V0;
+    constexpr bool SHARE = UNIT && MLO == 0 && AC::SELF;  // s[l] == a[l] for l <= lmax
     if constexpr (MLO == 0 || AC::SELF) {
         // m = 0 chain, up to 2 lmax when the self moments are held
         constexpr int LTOP = AC::SELF ? 2 * LMAX : LMAX;
-        const T w2 = w * w;
+        const T w2 = UNIT ? (T)1 : w * w;
         T r0 = (T)1, r1 = z;
-        if constexpr (MLO == 0) A.a[0 - V0] += w;
-        if constexpr (AC::SELF) A.s[0] += w2;
+        if constexpr (MLO == 0) A.a[0 - V0] += UNIT ? (T)1 : w;
+        if constexpr (AC::SELF && !SHARE) A.s[0] += w2;
         if constexpr (LTOP >= 1) {
-            if constexpr (MLO == 0 && LMAX >= 1) A.a[1 - V0] = fma(w, r1, A.a[1 - V0]);
-            if constexpr (AC::SELF) A.s[1] = fma(w2, r1, A.s[1]);
+            if constexpr (MLO == 0 && LMAX >= 1) A.a[1 - V0] = UNIT ? A.a[1 - V0] + r1 : fma(w, r1, A.a[1 - V0]);
+            if constexpr (AC::SELF && !(SHARE && 1 <= LMAX)) A.s[1] = UNIT ? A.s[1] + r1 : fma(w2, r1, A.s[1]);
         }
 #pragma unroll
         for (int l = 2; l <= LTOP; ++l) {
             const T r2 = fma(z, r1, -beta<T>(l, 0) * r0);
-            if (MLO == 0 && l <= LMAX) A.a[l - V0] = fma(w, r2, A.a[l - V0]);
-            if (AC::SELF) A.s[l] = fma(w2, r2, A.s[l]);
+            if (MLO == 0 && l <= LMAX) A.a[l - V0] = UNIT ? A.a[l - V0] + r2 : fma(w, r2, A.a[l - V0]);
+            if (AC::SELF && !(SHARE && l <= LMAX)) A.s[l] = UNIT ? A.s[l] + r2 : fma(w2, r2, A.s[l]);
             r0 = r1;
             r1 = r2;
         }
     }
     if constexpr (MHI >= 1) {
         // c_m = w (x - i y)^m
-        T cr = w * x, ci = -(w * y);
+        T cr = UNIT ? x : w * x, ci = UNIT ? -y : -(w * y);
 #pragma unroll
         for (int m = 1; m <= MHI; ++m) {
             if (m > 1) {
@@ -722,7 +726,7 @@ __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) 
     }
 }
 
-template <typename T, int LMAX, int G>
+template <typename T, int LMAX, int G, bool UNIT>
 __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
     using AC = Acc<T, LMAX, G>;
     constexpr int NV = n_values(LMAX);
@@ -761,7 +765,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
             const float4 r2 = t + 2 < n ? rec[t + 2] : make_float4(1.f, 0.f, 0.f, 0.f);
             const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
             const float inv = __builtin_amdgcn_rsqf(d2);
-            add_hit<T, LMAX, G>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
+            add_hit<T, LMAX, G, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
             r0 = r1;
             r1 = r2;
         }
@@ -791,13 +795,17 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
             double inv = __builtin_amdgcn_rsq(r2);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
-            add_hit<T, LMAX, G>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d0.w);
+            add_hit<T, LMAX, G, UNIT>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d0.w);
             e0 = e1;
             e1 = e2;
             d0 = d1;
         }
     }
     if (!active) return;
+    if constexpr (UNIT && AC::MLO == 0 && AC::SELF) {
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l - AC::V0];
+    }
     T* A = reinterpret_cast<T*>(a.A);
     const int64_t ld = a.ldA;
 #pragma unroll
@@ -814,7 +822,11 @@ hipError_t launch_alm_one(const AlmArgs& a, hipStream_t s) {
     const int64_t nprim = a.p_end - a.p_begin;
     const int64_t nwaves = ((nprim + 255) / 256) * a.nb * 4;
     const int64_t nwg = (nwaves + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_pair_alm<T, LMAX, G>), dim3((unsigned)nwg), dim3(64), 0, s, a);
+    // unit weights: the FP32 single-launch kernel shares the m = 0 sums
+    if (sizeof(T) == 4 && G == 0 && a.unit_w)
+        hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, true>), dim3((unsigned)nwg), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, false>), dim3((unsigned)nwg), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
