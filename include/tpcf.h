@@ -60,7 +60,10 @@ typedef enum {
     TPCF_PREC_FP32 = 1,         /* FP32 pair pass, FP32 MFMA contraction, FP64 final sums     */
     TPCF_PREC_MIXED_BF16X3 = 2, /* FP32 pair pass, split-BF16 contraction: x = hi + lo (BF16),
                                    products hi.hi + hi.lo + lo.hi on BF16 MFMA, FP32
-                                   accumulation per subchunk, FP64 final sums                 */
+                                   accumulation per subchunk, FP64 final sums. With weights
+                                   (d_w given) the six-product split of MIXED_BF16X6 is
+                                   used: data and random terms cancel in the sum over
+                                   primaries and would magnify the three-product error   */
     TPCF_PREC_MIXED_BF16X6 = 3  /* as above with x = hi + mid + lo and six products (every
                                    product above 2^-24 relative): FP32-level accuracy for
                                    sparse bins at twice the BF16 MFMA work                    */

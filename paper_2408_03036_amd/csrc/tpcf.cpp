@@ -747,7 +747,8 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     c.part64 = P<double>(h->d_part);
     c.gsize = h->gsize;
     c.goff = P<int64_t>(h->d_goff);
-    c.mode = h->mode;
+    // weighted catalogues (data minus randoms) need the six-product split
+    c.mode = (h->mode == TPCF_PREC_MIXED_BF16X3 && !h->unit_w) ? TPCF_PREC_MIXED_BF16X6 : h->mode;
     c.unit_weights = h->unit_w ? 1 : 0;
     c.pw = P<float>(h->d_pw);
     HIPCHK(launch_contract(c, h->stream));
@@ -875,6 +876,9 @@ tpcf_status validate_config(const tpcf_config* c) {
     if (c->flags & ~(uint32_t)(TPCF_F_KEEP_DEGENERATE | TPCF_F_PAPER_LITERAL)) return TPCF_ERR_ARG;
     const int mode = c->precision;
     if (contract_lds_bytes(mode, c->nbins, c->lmax) > 160 * 1024) return TPCF_ERR_RANGE;
+    if (mode == TPCF_PREC_MIXED_BF16X3 &&
+        contract_lds_bytes(TPCF_PREC_MIXED_BF16X6, c->nbins, c->lmax) > 160 * 1024)
+        return TPCF_ERR_RANGE;
     return TPCF_OK;
 }
 

@@ -7,7 +7,9 @@ of a slice of primaries (Sec. 4.2, eq. (alm)) needs only those primaries'
 neighbours. The batched run of 64 catalogues is checked by properties that hold
 at any size: each catalogue of the batch equals the same catalogue run alone,
 bit for bit; the mixed path agrees with the FP64 path within the split-BF16
-tolerance; and one catalogue's a_lm slice matches the oracle.
+tolerance; and one catalogue's a_lm slice matches the oracle. A data + 5x
+randoms catalogue with data-minus-randoms weights checks every precision
+against the FP64 path at full size.
 """
 import sys
 
@@ -73,6 +75,51 @@ def test_alm_slice_400k_mixed(torch):
     err = alm_slice_error(torch, pos, 1500.0, np.linspace(10.0, 130.0, 13), 10,
                           T.PREC_MIXED_BF16X3, 250_001)
     say(f"  a_lm slice rel err {err:.3e}")
+    assert err < 1e-5
+
+
+def test_data_minus_randoms_large(torch):
+    """10^5 clustered data points plus 5x uniform randoms with weights
+    1 and -N_D/N_R in a 1500 Mpc/h box, 12 bins over [10, 130], lmax 10,
+    L <= 4: every precision against the FP64 path, and an a_lm slice of the
+    FP32 pair pass against the oracle."""
+    box, edges, lmax = 1500.0, np.linspace(10.0, 130.0, 13), 10
+    mults = O.all_multipoles(lmax, 4)
+    nd = 100_000
+    say("  data + 5x randoms")
+    D = zeldovich_host(torch, nd, box, 5.0, 0.8, C.catalogue_seed(5))
+    pos = np.vstack([D, C.randoms(5 * nd, box, C.randoms_seed(5))])
+    w = C.dr_weights(nd, 5 * nd)
+    P, W = torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda()
+    outs, pairs = {}, set()
+    for prec in (T.PREC_FP64, T.PREC_FP32, T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6):
+        h = T.Handle(box, edges, lmax, precision=prec)
+        h.build_grid(P, W, nd)
+        h.alm_accumulate()
+        h.contract()
+        out = h.multipoles(mults)
+        h.sync()
+        pairs.add(h.pair_count())
+        h.close()
+        outs[prec] = out.cpu().numpy()
+    assert len(pairs) == 1
+    ref = outs[T.PREC_FP64]
+    tol = {T.PREC_FP32: 1e-5, T.PREC_MIXED_BF16X3: 1e-4, T.PREC_MIXED_BF16X6: 1e-5}
+    for prec, t in tol.items():
+        err = float(np.abs(outs[prec] - ref).max() / np.abs(ref).max())
+        say(f"  precision {prec}: rel err vs FP64 path {err:.3e}")
+        assert err < t, prec
+    h = T.Handle(box, edges, lmax, precision=T.PREC_FP32)
+    h.build_grid(P, W, nd)
+    h.alm_accumulate()
+    got = h.get_alm(31_000, SLICE).cpu().numpy()
+    h.sync()
+    h.close()
+    ref_alm = O.estimate(pos, box, edges, lmax, w=w, prim_first=31_000, prim_count=SLICE, want_alm=True,
+                         want_nnn=False).alm
+    mask = np.tril(np.ones((lmax + 1, lmax + 1), dtype=bool))
+    err = float(np.abs(got[..., mask] - ref_alm[..., mask]).max() / np.abs(ref_alm[..., mask]).max())
+    say(f"  weighted a_lm slice rel err {err:.3e}")
     assert err < 1e-5
 
 
