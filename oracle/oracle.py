@@ -54,6 +54,15 @@ def lib():
         _lib.oracle_ylm.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_void_p]
         _lib.oracle_ylm.restype = None
+        _lib.oracle_legendre_bin_integral.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        _lib.oracle_legendre_bin_integral.restype = ctypes.c_double
+        _lib.oracle_xi_counts.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        _lib.oracle_xi_counts.restype = ctypes.c_int
+        _lib.oracle_xi_multipoles.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                              ctypes.c_void_p]
+        _lib.oracle_xi_multipoles.restype = ctypes.c_int
     return _lib
 
 
@@ -151,3 +160,38 @@ def run(pos, box, edges, lmax, mults, w=None, n_data=None, subtract_self=True, n
     res = estimate(pos, box, edges, lmax, w=w, subtract_self=subtract_self, nthreads=nthreads)
     re, im = multipoles(res.nnn, n_data, box, edges, lmax, mults, literal=literal)
     return re, im, res
+
+
+# ------------------------------------------------------------------ 2PCF (Sec. 4.1)
+
+
+def legendre_bin_integral(l: int, a: float, b: float) -> float:
+    """Integral of P_l over [a, b]."""
+    return lib().oracle_legendre_bin_integral(int(l), float(a), float(b))
+
+
+def xi_counts(pos, box, edges, nmu, nthreads=0) -> np.ndarray:
+    """DD(r, mu): int64 [nbins][nmu] ordered-pair counts, mu = rhat . z over [-1, 1]."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    nb = edges.shape[0] - 1
+    out = np.zeros((nb, nmu), dtype=np.int64)
+    rc = lib().oracle_xi_counts(pos.shape[0], pos.ctypes.data, float(box), nb, edges.ctypes.data,
+                                int(nmu), int(nthreads), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_xi_counts rejected its arguments")
+    return out
+
+
+def xi_multipoles(counts, n_data, box, edges, ells) -> np.ndarray:
+    """xi_l(r_b) of eq. (xi_meas_leg) from DD(r, mu): float64 [len(ells)][nbins]."""
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    nb, nmu = counts.shape
+    el = np.ascontiguousarray(np.array(ells, dtype=np.int32).reshape(-1))
+    out = np.zeros((el.shape[0], nb))
+    rc = lib().oracle_xi_multipoles(counts.ctypes.data, int(n_data), float(box), nb, edges.ctypes.data,
+                                    int(nmu), el.shape[0], el.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_xi_multipoles rejected its arguments")
+    return out

@@ -30,6 +30,10 @@
  *  - the output is the coefficient of the TripoSH basis of eq. (TSHbasis)
  *    (Schmidt semi-normalised y), so a Poisson catalogue gives c_000 = 1.
  *
+ * The same file holds the anisotropic 2PCF of Sec. 4.1 (pair counts in
+ * (r, mu), eq. (xi_natest), Legendre multipoles eq. (xi_meas_leg)); its
+ * readings are listed with it below.
+ *
  * Y_lm is orthonormal with the Condon-Shortley phase, evaluated from theta/phi
  * trigonometry and the textbook associated-Legendre recurrence in l.
  * The Wigner 3j symbols use Racah's single-sum formula.
@@ -426,5 +430,195 @@ int oracle_multipoles(const double* nnn, int64_t n_data, double box, int nbins,
             }
     }
     free(V);
+    return 0;
+}
+
+/* ================================================================ 2PCF
+ *
+ * Anisotropic two-point function of Sec. 4.1: pair counts DD(r, mu) in bins
+ * of separation r and of mu = rhat . z (the common line of sight along z),
+ * the natural estimator xi(r, mu) = DD / RR - 1 of eq. (xi_natest) with the
+ * analytic random-pair counts of a periodic box, and its Legendre multipoles
+ * of eq. (xi_meas_leg).
+ *
+ * Readings taken where the paper is silent:
+ *  - pairs are ordered (p, j) with j != p; the radial bin is that of the
+ *    3PCF above (half-open, from r^2 = dx*dx + dy*dy + dz*dz evaluated left
+ *    to right, minimum image, r = 0 dropped);
+ *  - mu covers [-1, 1] in nmu equal bins; with r = sqrt(r^2) and
+ *    mu = dz / r the bin is k = floor((mu + 1) * (nmu / 2)), every operation
+ *    rounded in double, and k is clamped to [0, nmu - 1] (so mu = 1 falls in
+ *    the last bin);
+ *  - RR(b, k) = N (N - 1) V_b / (nmu L^3): N (N - 1) ordered pairs of
+ *    uniform points, the fraction V_b / L^3 of them in shell b (exact for
+ *    e_nb <= L/2) spread evenly over mu;
+ *  - xi(r, mu) is constant inside a mu bin, so the integral of eq.
+ *    (xi_meas_leg) becomes sum_k xi(r_b, mu_k) times the exact integral of
+ *    P_l over the bin.
+ */
+
+/* P_l(x) for l = 0..lmax by Bonnet's recurrence (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}. */
+static void legendre_all(int lmax, double x, double* P)
+{
+    P[0] = 1.0;
+    if (lmax >= 1) P[1] = x;
+    for (int l = 1; l < lmax; ++l)
+        P[l + 1] = ((2.0 * l + 1.0) * x * P[l] - (double)l * P[l - 1]) / (double)(l + 1);
+}
+
+/* Integral of P_l over [a, b]: b - a for l = 0, otherwise
+ * [P_{l+1} - P_{l-1}] / (2l + 1) between a and b (from
+ * (2l+1) P_l = d/dx (P_{l+1} - P_{l-1})). */
+double oracle_legendre_bin_integral(int l, double a, double b)
+{
+    if (l < 0) return 0.0;
+    if (l == 0) return b - a;
+    double Pa[64], Pb[64];
+    if (l + 1 >= 64) return 0.0;
+    legendre_all(l + 1, a, Pa);
+    legendre_all(l + 1, b, Pb);
+    return ((Pb[l + 1] - Pb[l - 1]) - (Pa[l + 1] - Pa[l - 1])) / (2.0 * l + 1.0);
+}
+
+/*
+ * DD(r, mu) of the points (pos, n) in a periodic box: counts[b * nmu + k]
+ * (int64) of ordered pairs in radial bin b and mu bin k.
+ * Returns 0, or -1 on invalid arguments.
+ */
+int oracle_xi_counts(int64_t n, const double* pos, double box, int nbins, const double* edges,
+                     int nmu, int nthreads, int64_t* counts)
+{
+    const double L = box;
+    const int nb = nbins;
+    if (n < 1 || !(L > 0.0) || nb < 1 || nmu < 1 || !pos || !edges || !counts) return -1;
+    for (int b = 0; b < nb; ++b)
+        if (!(edges[b + 1] > edges[b])) return -1;
+    if (edges[0] < 0.0 || edges[nb] > 0.5 * L) return -1;
+
+    double* x = (double*)malloc(sizeof(double) * 3 * n);
+    for (int64_t i = 0; i < 3 * n; ++i) x[i] = wrap_coord(pos[i], L);
+    double* e2 = (double*)malloc(sizeof(double) * (nb + 1));
+    for (int b = 0; b <= nb; ++b) e2[b] = edges[b] * edges[b];
+    const double half = (double)nmu / 2.0;
+
+    /* Linked-list cell partition with cells of side >= r_max (27 neighbour
+     * cells), or one cell when the box holds fewer than 3 per side. */
+    int nc = (int)floor(L / edges[nb]);
+    if (nc < 3) nc = 1;
+    const int64_t ncell = (int64_t)nc * nc * nc;
+    int64_t* head = (int64_t*)malloc(sizeof(int64_t) * ncell);
+    int64_t* next = (int64_t*)malloc(sizeof(int64_t) * n);
+    for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int cx = (int)(x[3 * i] / L * nc), cy = (int)(x[3 * i + 1] / L * nc),
+            cz = (int)(x[3 * i + 2] / L * nc);
+        if (cx >= nc) cx = nc - 1;
+        if (cy >= nc) cy = nc - 1;
+        if (cz >= nc) cz = nc - 1;
+        int64_t c = ((int64_t)cx * nc + cy) * nc + cz;
+        next[i] = head[c];
+        head[c] = i;
+    }
+
+    const size_t nh = (size_t)nb * nmu;
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    int64_t* hist = (int64_t*)calloc((size_t)nthr * nh, sizeof(int64_t));
+
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthr)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int64_t* my = hist + (size_t)tid * nh;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 256)
+#endif
+        for (int64_t p = 0; p < n; ++p) {
+            const double xp = x[3 * p], yp = x[3 * p + 1], zp = x[3 * p + 2];
+            int cx = (int)(xp / L * nc), cy = (int)(yp / L * nc), cz = (int)(zp / L * nc);
+            if (cx >= nc) cx = nc - 1;
+            if (cy >= nc) cy = nc - 1;
+            if (cz >= nc) cz = nc - 1;
+            const int span = nc == 1 ? 0 : 1;
+            for (int ox = -span; ox <= span; ++ox)
+                for (int oy = -span; oy <= span; ++oy)
+                    for (int oz = -span; oz <= span; ++oz) {
+                        int qx = (cx + ox + nc) % nc, qy = (cy + oy + nc) % nc,
+                            qz = (cz + oz + nc) % nc;
+                        int64_t c = ((int64_t)qx * nc + qy) * nc + qz;
+                        for (int64_t j = head[c]; j >= 0; j = next[j]) {
+                            if (j == p) continue;
+                            double dx = x[3 * j] - xp, dy = x[3 * j + 1] - yp,
+                                   dz = x[3 * j + 2] - zp;
+                            dx -= L * rint(dx / L);
+                            dy -= L * rint(dy / L);
+                            dz -= L * rint(dz / L);
+                            double r2 = dx * dx;
+                            r2 += dy * dy;
+                            r2 += dz * dz;
+                            if (r2 == 0.0) continue;
+                            if (r2 < e2[0] || r2 >= e2[nb]) continue;
+                            int b = 0;
+                            while (!(r2 >= e2[b] && r2 < e2[b + 1])) ++b;
+                            const double r = sqrt(r2);
+                            const double mu = dz / r;
+                            const double t = (mu + 1.0) * half;
+                            int k = (int)floor(t);
+                            if (k < 0) k = 0;
+                            if (k > nmu - 1) k = nmu - 1;
+                            my[(size_t)b * nmu + k] += 1;
+                        }
+                    }
+        }
+    }
+    for (size_t i = 0; i < nh; ++i) {
+        int64_t s = 0;
+        for (int t = 0; t < nthr; ++t) s += hist[(size_t)t * nh + i];
+        counts[i] = s;
+    }
+    free(hist);
+    free(head);
+    free(next);
+    free(e2);
+    free(x);
+    return 0;
+}
+
+/*
+ * Legendre multipoles of the natural estimator (eq. (xi_natest), (xi_meas_leg)):
+ *   xi(r_b, mu_k) = DD(b, k) / RR(b, k) - 1,  RR(b, k) = N (N-1) V_b / (nmu L^3),
+ *   xi_l(r_b) = (2l + 1) / 2 * sum_k xi(r_b, mu_k) * integral of P_l over bin k,
+ * with the mu bin edges mu_k = -1 + 2k / nmu.
+ * out: n_ell * nbins, [i][b] for l = ells[i]. Returns 0 or -1.
+ */
+int oracle_xi_multipoles(const int64_t* counts, int64_t n_data, double box, int nbins,
+                         const double* edges, int nmu, int n_ell, const int* ells, double* out)
+{
+    if (n_data < 2 || !(box > 0.0) || nbins < 1 || nmu < 1 || n_ell < 0) return -1;
+    const double nd = (double)n_data;
+    const double L3 = box * box * box;
+    for (int i = 0; i < n_ell; ++i) {
+        const int l = ells[i];
+        if (l < 0 || l > 60) return -1;
+        for (int b = 0; b < nbins; ++b) {
+            const double V = 4.0 * OR_PI / 3.0 *
+                             (edges[b + 1] * edges[b + 1] * edges[b + 1] - edges[b] * edges[b] * edges[b]);
+            const double rr = nd * (nd - 1.0) * V / ((double)nmu * L3);
+            double s = 0.0;
+            for (int k = 0; k < nmu; ++k) {
+                const double lo = -1.0 + 2.0 * (double)k / (double)nmu;
+                const double hi = -1.0 + 2.0 * (double)(k + 1) / (double)nmu;
+                const double xi = (double)counts[(size_t)b * nmu + k] / rr - 1.0;
+                s += xi * oracle_legendre_bin_integral(l, lo, hi);
+            }
+            out[(size_t)i * nbins + b] = (2.0 * l + 1.0) / 2.0 * s;
+        }
+    }
     return 0;
 }
