@@ -11,6 +11,11 @@ Prints ONE JSON line. `value` is pairs/s into a_lm(r) (ordered in-shell pairs
 of all catalogues per step / seconds per step) for the mixed path.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+With --workload xi it times instead the anisotropic 2PCF of Sec. 4.1 on one
+catalogue of the paper's halo density (7.2e5 clustered points, 1500 Mpc/h
+box): DD(r, mu) in 30 x 5 Mpc/h radial bins and mu bins of 0.01, then the
+Legendre multipoles l = 0, 2, 4; `value` is ordered pairs counted per second.
 """
 from __future__ import annotations
 
@@ -132,6 +137,95 @@ def cpu_baseline(pos_np, box, edges, lmax, target_s=15.0):
                       f"NNN accumulation) in {t1:.1f} s"}
 
 
+# Algorithmic FP32 work per counted pair: separation (3), r^2 (5), r (1),
+# radial bin (2), mu and its bin (3).
+XI_FLOP_PER_PAIR = 14
+
+
+def xi_cpu_baseline(pos_np, box, edges, nmu, target_s=15.0):
+    """Times the CPU oracle's DD(r, mu) on a subsample of the catalogue (the
+    points are in random order, so the first n are a uniform subsample),
+    sized for about target_s seconds; pairs/s."""
+    from oracle import oracle as O
+    try:
+        nthr = len(os.sched_getaffinity(0))
+    except Exception:
+        nthr = os.cpu_count() or 1
+    nthr = min(nthr, 16)
+    n = min(pos_np.shape[0], 50_000)
+    t0 = time.perf_counter()
+    npairs = int(O.xi_counts(pos_np[:n], box, edges, nmu, nthreads=nthr).sum())
+    t1 = time.perf_counter() - t0
+    # pairs grow as n^2: pick n for about target_s seconds
+    n2 = int(min(pos_np.shape[0], n * math.sqrt(max(target_s / max(t1, 1e-3), 1.0))))
+    t0 = time.perf_counter()
+    npairs = int(O.xi_counts(pos_np[:n2], box, edges, nmu, nthreads=nthr).sum())
+    t1 = time.perf_counter() - t0
+    return {"value": npairs / t1, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
+            "sample": f"DD(r, mu) of the first {n2} points of the catalogue ({npairs} pairs) in {t1:.1f} s"}
+
+
+def bench_xi(args):
+    """The anisotropic 2PCF (Sec. 4.1): grid build, DD(r, mu) and multipoles per step."""
+    import torch
+    from paper_2408_03036_amd import catalogs as C
+    from paper_2408_03036_amd import tpcf as T
+
+    box, n, sigma, fgrowth = 1500.0, 720_000, 5.0, 0.8
+    edges = np.linspace(0.0, 150.0, 31)
+    nmu, ells = 200, [0, 2, 4]
+    print("[bench] generating the 2PCF catalogue on the GPU", file=sys.stderr, flush=True)
+    pos = C.zeldovich_torch(n, box, sigma, fgrowth, C.catalogue_seed(60), grid=256, device="cuda:0")
+    torch.cuda.synchronize()
+    h = T.Handle(box, edges, 0, precision=T.PREC_FP32, grid_refine=args.refine)
+    h.set_timing(True)
+
+    def step():
+        h.build_grid(pos)
+        dd = h.xi_count(nmu)
+        return dd, h.xi_multipoles(dd, n, ells)
+
+    print(f"[bench] 2PCF: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    h.sync()
+    h.stage_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dd, xi = step()
+    h.sync()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ms, nl = h.stage_times()
+    h.close()
+    npairs = int(dd.sum().item())
+    t_cnt = ms[5] / max(nl[5], 1) / 1e3
+    achieved = npairs * XI_FLOP_PER_PAIR / t_cnt
+    roof = {"kernel": "k_xi_count (DD(r, mu) pair counts)", "bound": "alu",
+            "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+            "flop_per_pair": XI_FLOP_PER_PAIR, "avg_launch_ms": t_cnt * 1e3, "launches_per_step": nl[5] / args.steps}
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = xi_cpu_baseline(pos.cpu().numpy(), box, edges, nmu)
+    line = {
+        "metric": "pairs/s into DD(r, mu) (anisotropic 2PCF, Sec. 4.1), 1 GPU",
+        "value": npairs / dt, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"2PCF of one Zel'dovich+RSD catalogue: {n} points in a {box:.0f} Mpc/h box, "
+                               f"30 radial bins [0,150] Mpc/h, {nmu} mu bins over [-1,1], l = 0, 2, 4",
+                   "points": n, "pairs_per_step": npairs, "parallelism": "single GPU"},
+        "stages_ms": {"grid_ms": ms[0] / args.steps, "xi_count_ms": ms[5] / args.steps,
+                      "xi_multipoles_ms": ms[4] / args.steps},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,12 +236,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--refine", type=int, default=0)
+    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi"],
+                    help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the catalogue batch would be split across GPUs by whole catalogues).",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "xi":
+        bench_xi(args)
+        return
 
     import torch
     from paper_2408_03036_amd import tpcf as T

@@ -22,6 +22,18 @@
  * separation is used; pairs at zero separation and degenerate triangles
  * (j == k) are excluded.
  *
+ * The same handle also measures the anisotropic two-point function of Sec.
+ * 4.1 on the neighbour grid of step 1 (tpcf_xi_count, tpcf_xi_multipoles):
+ *
+ *   DD(b, k)  = ordered pairs (p, j != p) with |x_j - x_p| in radial bin b and
+ *               mu = (z_j - z_p) / |x_j - x_p| (line of sight z) in bin k of
+ *               nmu equal bins over [-1, 1]
+ *   xi(r_b, mu_k) = DD(b, k) / RR(b, k) - 1,  RR(b, k) = N (N-1) V_b / (nmu L^3)
+ *               (the natural estimator of eq. (xi_natest) with the analytic
+ *                random pairs of a periodic box)
+ *   xi_l(r_b) = (2l+1)/2 sum_k xi(r_b, mu_k) * integral of P_l over bin k
+ *               (eq. (xi_meas_leg) with xi constant inside a mu bin).
+ *
  * Conventions for every call:
  *  - Pointers prefixed d_ are DEVICE pointers on the handle's device (for
  *    example torch.Tensor.data_ptr()); h_ are HOST pointers. The caller owns
@@ -159,6 +171,32 @@ tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n,
                               const int64_t* h_n_data, const double* d_pos, const double* d_w,
                               int32_t n_mult, const int32_t* h_l1l2L, double* d_out);
 
+/*
+ * Anisotropic 2PCF pair counts DD(r, mu) (Sec. 4.1) of the catalogue given to
+ * tpcf_build_grid, which must have been built without weights (d_w = NULL);
+ * the radial bins are the handle's edges. Requires tpcf_build_grid.
+ *  nmu     : mu bins over [-1, 1], 1 .. 4096, with nbins * nmu <= 16384.
+ *            With r^2 = dx*dx + dy*dy + dz*dz and mu = dz / sqrt(r^2), the
+ *            bin is floor((mu + 1) nmu / 2) evaluated in double, clamped to
+ *            nmu - 1 (mu = 1 falls in the last bin).
+ *  d_counts: nbins x nmu int64 (device), [b][k], overwritten. Every ordered
+ *            pair is counted, so DD(b, k) and DD(b, nmu-1-k) differ only
+ *            through pairs on a mu edge.
+ * Exact: the counts equal those of a double-precision evaluation of every pair.
+ */
+tpcf_status tpcf_xi_count(tpcf_handle h, int32_t nmu, int64_t* d_counts);
+
+/*
+ * Legendre multipoles xi_l(r_b) (eq. (xi_meas_leg)) of the natural estimator
+ * from pair counts d_counts (nbins x nmu int64, device, as written by
+ * tpcf_xi_count) of a catalogue of n_data >= 2 points in the handle's box.
+ *  h_ells: host array of n_ell (1 .. 64) orders l in 0 .. 60.
+ *  d_out : n_ell x nbins float64 (device).
+ * Needs no earlier step; reads d_counts on the handle's stream.
+ */
+tpcf_status tpcf_xi_multipoles(tpcf_handle h, int32_t nmu, const int64_t* d_counts, int64_t n_data,
+                               int32_t n_ell, const int32_t* h_ells, double* d_out);
+
 /* Waits for all work enqueued by h. */
 tpcf_status tpcf_sync(tpcf_handle h);
 
@@ -179,7 +217,8 @@ tpcf_status tpcf_rebinned_count(tpcf_handle h, int64_t* h_out);
  * each stage it enqueues; tpcf_stage_times then returns, after tpcf_sync, the
  * summed milliseconds of the stages since the last reset and resets them:
  *  h_ms[0] grid build, [1] pair binning, [2] pair harmonics (a_lm),
- *  [3] contraction, [4] finalisation; h_launches[k] counts the launches timed.
+ *  [3] contraction, [4] finalisation (3PCF and 2PCF multipoles), [5] 2PCF
+ *  pair counts; h_launches[k] counts the launches timed.
  * Either output may be NULL; at most n entries are written.
  */
 tpcf_status tpcf_set_timing(tpcf_handle h, int enable);

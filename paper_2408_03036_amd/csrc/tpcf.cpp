@@ -26,6 +26,7 @@ using namespace tpcf;
 namespace {
 
 constexpr uint32_t kMagic = 0x74706366u;  // "tpcf"
+constexpr int kStages = 6;                // timed stages (tpcf_stage_times)
 constexpr uint32_t kDead = 0xdeadbeefu;
 const double kPi = 3.14159265358979323846;
 
@@ -104,11 +105,14 @@ struct tpcf_handle_s {
     int64_t pairs = 0;
     bool pairs_valid = false;
 
+    // 2PCF
+    DevBuf d_xiq, d_xicoef, d_xirr, d_xiruns;
+
     // timing
     bool timing = false;
     std::vector<Timer> timers;
-    double ms[5] = {0, 0, 0, 0, 0};
-    int64_t nl[5] = {0, 0, 0, 0, 0};
+    double ms[kStages] = {0, 0, 0, 0, 0, 0};
+    int64_t nl[kStages] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -931,7 +935,8 @@ void tpcf_destroy(tpcf_handle h) {
                      &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
                      &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_scanw, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
-                     &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag};
+                     &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag,
+                     &h->d_xiq, &h->d_xicoef, &h->d_xirr, &h->d_xiruns};
     for (DevBuf* b : all) release(h, *b);
     h->magic = kDead;
     delete h;
@@ -1074,6 +1079,139 @@ tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n, c
     return TPCF_OK;
 }
 
+tpcf_status tpcf_xi_count(tpcf_handle h, int32_t nmu, int64_t* d_counts) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_counts) return fail(h, TPCF_ERR_ARG, "d_counts is NULL");
+    if (nmu < 1 || nmu > 4096) return fail(h, TPCF_ERR_RANGE, "nmu must be in 1 .. 4096");
+    if ((int64_t)h->nb * nmu > kXiMaxBins) return fail(h, TPCF_ERR_RANGE, "nbins * nmu exceeds 16384");
+    if (h->stage < 1) return fail(h, TPCF_ERR_STATE, "tpcf_build_grid must come first");
+    if (h->ncat != 1) return fail(h, TPCF_ERR_STATE, "the 2PCF counts the catalogue of tpcf_build_grid");
+    if (!h->unit_w) return fail(h, TPCF_ERR_ARG, "the 2PCF pair counts take unit weights (d_w = NULL)");
+    // half stencil: every unordered pair of distinct cells once, and the home cell
+    std::vector<StencilRun> half;
+    for (const StencilRun& r : h->runs) {
+        if (h->g.single || r.ox > 0 || (r.ox == 0 && r.oy > 0)) {
+            half.push_back(r);
+        } else if (r.ox == 0 && r.oy == 0) {
+            if (r.oz_lo <= 0 && r.oz_hi >= 0) half.push_back({0, 0, 0, 0});
+            if (r.oz_hi >= 1) half.push_back({0, 0, std::max(r.oz_lo, 1), r.oz_hi});
+        }
+    }
+    const int npmax = 2 * (int)half.size();
+    if (xi_lds_bytes(h->nb, nmu, npmax) > 160 * 1024)
+        return fail(h, TPCF_ERR_RANGE, "the (r, mu) histogram does not fit the LDS");
+    HIPCHK(hipSetDevice(h->device));
+    tpcf_status st = check_nonfinite(h);  // also completes the copy of item_cat
+    if (st != TPCF_OK) return st;
+    if ((st = upload(h, h->d_xiruns, half.data(), sizeof(StencilRun) * std::max<size_t>(half.size(), 1))) != TPCF_OK)
+        return st;
+    if ((st = ensure(h, h->d_xiq, sizeof(int) * 8 * 32)) != TPCF_OK) return st;
+    HIPCHK(launch_fill_i32(P<int>(h->d_xiq), 8 * 32, 0, h->stream));
+    HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(d_counts), (int64_t)h->nb * nmu, 0ull,
+                           h->stream));
+    XiArgs a{};
+    a.pf = P<float4>(h->d_pf);
+    a.pd = P<double4>(h->d_pd);
+    a.cell_start = P<int>(h->d_start);
+    a.runs = P<StencilRun>(h->d_xiruns);
+    a.nruns = (int)half.size();
+    {
+        const int k = h->g.k, K2 = 2 * k + 1;
+        a.home_code = (k * K2 + k) * K2 + k;
+    }
+    a.g = h->g;
+    a.nb = h->nb;
+    a.e2 = P<double>(h->d_e2);
+    a.e2f = P<float>(h->d_e2f);
+    a.guard = P<float>(h->d_guard);
+    a.uniform = h->uniform;
+    a.e0f = (float)h->edges[0];
+    a.inv_dr = h->inv_dr;
+    a.delta = h->delta;
+    a.inv_boxf = (float)(1.0 / h->cfg.box);
+    a.nmu = nmu;
+    a.hmu = nmu / 2.0;
+    a.hmu_f = (float)a.hmu;
+    // Error bound of t = (mu + 1) nmu / 2 in FP32. Each separation component
+    // is within dd of its exact value (the bound of the radial guard bands),
+    // so mu = dz / r is within (1 + sqrt 3) dd / r, plus a few ulp of the
+    // square root, reciprocal and product; the fused t adds half an ulp.
+    {
+        const double span = h->g.single ? h->cfg.box : (h->g.k + 1) * h->g.h;
+        const double dd = 4.0 * ulp32(span);
+        a.gmu_a = (float)(a.hmu * (1.0 + std::sqrt(3.0)) * dd);
+        a.gmu_b = (float)(2.0 * (a.hmu * 4.0 * std::ldexp(1.0, -23) + nmu * std::ldexp(1.0, -24)));
+    }
+    a.item_start = P<int>(h->d_istart);
+    a.item_cell = P<int>(h->d_icell);
+    a.nitems = h->item_cat[1] - h->item_cat[0];
+    a.npmax = npmax;
+    a.counts = reinterpret_cast<unsigned long long*>(d_counts);
+    a.queue = P<int>(h->d_xiq);
+    Timer t;
+    t_begin(h, 5, t);
+    HIPCHK(launch_xi_count(a, h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_xi_multipoles(tpcf_handle h, int32_t nmu, const int64_t* d_counts, int64_t n_data,
+                               int32_t n_ell, const int32_t* h_ells, double* d_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_counts || !d_out || !h_ells) return fail(h, TPCF_ERR_ARG, "NULL counts, ells or output");
+    if (nmu < 1 || nmu > 4096) return fail(h, TPCF_ERR_RANGE, "nmu must be in 1 .. 4096");
+    if (n_data < 2) return fail(h, TPCF_ERR_ARG, "n_data must be >= 2");
+    if (n_ell < 1 || n_ell > 64) return fail(h, TPCF_ERR_ARG, "n_ell must be in 1 .. 64");
+    for (int i = 0; i < n_ell; ++i)
+        if (h_ells[i] < 0 || h_ells[i] > 60) return fail(h, TPCF_ERR_ARG, "multipole orders must be in 0 .. 60");
+    HIPCHK(hipSetDevice(h->device));
+    // c_lk = (2l+1)/2 times the integral of P_l over mu bin k, by 32-point
+    // Gauss-Legendre quadrature on the bin (exact for the degrees allowed)
+    std::vector<double> gx, gw;
+    gauss_legendre(32, gx, gw);
+    std::vector<double> coef((size_t)n_ell * nmu);
+    for (int i = 0; i < n_ell; ++i) {
+        const int l = h_ells[i];
+        for (int k = 0; k < nmu; ++k) {
+            const double lo = -1.0 + 2.0 * k / nmu, hi = -1.0 + 2.0 * (k + 1) / nmu;
+            const double c = 0.5 * (lo + hi), hw = 0.5 * (hi - lo);
+            double s = 0.0;
+            for (size_t q = 0; q < gx.size(); ++q) {
+                const double x = c + hw * gx[q];
+                double p0 = 1.0, p1 = x;
+                double pl = l == 0 ? 1.0 : x;
+                for (int n = 1; n < l; ++n) {
+                    pl = ((2.0 * n + 1.0) * x * p1 - n * p0) / (n + 1.0);
+                    p0 = p1;
+                    p1 = pl;
+                }
+                s += gw[q] * pl;
+            }
+            coef[(size_t)i * nmu + k] = 0.5 * (2.0 * l + 1.0) * hw * s;
+        }
+    }
+    // analytic random pairs of one (r, mu) bin in a periodic box
+    std::vector<double> rr(h->nb);
+    const double nd = (double)n_data, L3 = h->cfg.box * h->cfg.box * h->cfg.box;
+    for (int b = 0; b < h->nb; ++b) rr[b] = nd * (nd - 1.0) * h->vol[b] / (nmu * L3);
+    tpcf_status st;
+    if ((st = upload(h, h->d_xicoef, coef.data(), sizeof(double) * coef.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_xirr, rr.data(), sizeof(double) * rr.size())) != TPCF_OK) return st;
+    XiFinalArgs a{};
+    a.counts = reinterpret_cast<const long long*>(d_counts);
+    a.nb = h->nb;
+    a.nmu = nmu;
+    a.n_ell = n_ell;
+    a.coef = P<double>(h->d_xicoef);
+    a.rr = P<double>(h->d_xirr);
+    a.out = d_out;
+    Timer t;
+    t_begin(h, 4, t);
+    HIPCHK(launch_xi_finalize(a, h->stream));
+    t_end(h, t);
+    return TPCF_OK;
+}
+
 tpcf_status tpcf_sync(tpcf_handle h) {
     if (!alive(h)) return TPCF_ERR_ARG;
     HIPCHK(hipSetDevice(h->device));
@@ -1123,11 +1261,11 @@ tpcf_status tpcf_stage_times(tpcf_handle h, int32_t n, double* h_ms, int64_t* h_
         hipEventDestroy(t.b);
     }
     h->timers.clear();
-    for (int i = 0; i < 5 && i < n; ++i) {
+    for (int i = 0; i < kStages && i < n; ++i) {
         if (h_ms) h_ms[i] = h->ms[i];
         if (h_launches) h_launches[i] = h->nl[i];
     }
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < kStages; ++i) {
         h->ms[i] = 0.0;
         h->nl[i] = 0;
     }

@@ -135,6 +135,46 @@ struct AlmArgs {
 };
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s);
 
+// 2PCF pair counts (tpcf_xi.hip)
+constexpr int kXiMaxBins = 16384;  // nb * nmu: one uint32 LDS counter per (r, mu) bin
+struct XiArgs {
+    const float4* pf;        // sorted (xr, yr, zr, iz) cell-relative FP32
+    const double4* pd;       // sorted (x, y, z, w) FP64 wrapped
+    const int* cell_start;   // [ncell+1]
+    const StencilRun* runs;  // half stencil: offsets positive in (x, y, z) order and the home cell
+    int nruns;
+    int home_code;           // stencil code of the home cell
+    Grid g;
+    int nb;
+    const double* e2;        // [nb+1] squared edges (FP64)
+    const float* e2f;        // [nb+1] squared edges (FP32)
+    const float* guard;      // [nb+1] FP32 guard band around each squared edge
+    int uniform;             // bins equally spaced in r
+    float e0f, inv_dr, delta;// uniform bins: first edge, 1 / width, guard band in bin units
+    float inv_boxf;          // 1 / L (single-cell mode)
+    int nmu;                 // mu bins over [-1, 1]
+    float hmu_f;             // nmu / 2
+    double hmu;
+    float gmu_a, gmu_b;      // FP32 guard band of t = (mu + 1) nmu / 2: gmu_a / r + gmu_b
+    const int* item_start;   // [ncell+1] first work item of each cell
+    const int* item_cell;    // [items] cell of each work item
+    int64_t nitems;
+    int npmax;
+    unsigned long long* counts; // [nb * nmu] (zeroed before the launch)
+    int* queue;              // [8 * 32] work cursors, one per XCD range (zeroed)
+};
+hipError_t launch_xi_count(const XiArgs& a, hipStream_t s);
+size_t xi_lds_bytes(int nb, int nmu, int npmax);
+
+struct XiFinalArgs {
+    const long long* counts; // [nb * nmu]
+    int nb, nmu, n_ell;
+    const double* coef;      // [n_ell * nmu] (2l+1)/2 * integral of P_l over mu bin k
+    const double* rr;        // [nb] analytic random pairs per (r, mu) bin
+    double* out;             // [n_ell * nb]
+};
+hipError_t launch_xi_finalize(const XiFinalArgs& a, hipStream_t s);
+
 // Contraction (tpcf_contract.hip)
 struct ContractArgs {
     const void* A;           // [nb][nvalues][ldA]

@@ -3,13 +3,14 @@
 // radial bin b, accumulate w_j conj(Y_lm(rhat_pj)) into a_lm(p, b).
 //
 // Two kernels:
-//  k_pair_bin  one workgroup per work item (up to 32 primaries of one cell of
+//  k_pair_bin  one workgroup per work item (up to 16 primaries of one cell of
 //              the neighbour grid). The cell's stencil of neighbour cells is
 //              one flattened candidate range, staged tile by tile in LDS in the
 //              home cell's frame; every wavefront tests the tile against its
-//              primaries. A first sweep counts the hits per (p, b), a second
-//              writes each hit straight to a per-primary list laid out bin by
-//              bin, with (offset, count) per (p, b).
+//              primaries and writes each hit into its primary's list, laid out
+//              bin by bin in regions predicted from the local density, with
+//              (offset, count) per (p, b). Primaries that overflow a region
+//              are redone by a second launch with exact counts.
 //  k_pair_alm  lane = one (primary, bin) list. A wavefront holds 64
 //              consecutive primaries of one bin; each lane walks its list and
 //              accumulates every harmonic in registers, so no cross-lane
@@ -28,72 +29,11 @@
 // r^2 = dx*dx + dy*dy + dz*dz against the squared edges. The FP32 path bins in
 // single precision from cell-relative coordinates and re-evaluates in FP64 the
 // rare pairs that fall inside a guard band around an edge.
-#include "tpcf_internal.h"
+#include "tpcf_cells.h"
 
 namespace tpcf {
 
 namespace {
-
-__device__ inline int lane_id() { return threadIdx.x & 63; }
-
-__device__ inline int lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-}
-
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// XCD-aware block remap: the hardware hands consecutive workgroups to the 8
-// XCDs in turn; this gives every XCD a contiguous range of logical blocks so
-// that neighbouring primaries share that XCD's L2. The map is a permutation
-// of [0, nblocks) when nblocks is a multiple of 8; launches round up to that.
-__device__ inline int64_t xcd_block(int64_t bid, int64_t nblocks) {
-    int64_t per = (nblocks + 7) / 8;
-    return (bid % 8) * per + bid / 8;
-}
-
-// Bin tables shared by the workgroup.
-struct BinTables {
-    double e2[kMaxBins + 1];
-    float e2f[kMaxBins + 1];
-    float guard[kMaxBins + 1];
-    uint32_t capoff[kMaxBins + 1];  // list layout of a primary: bin b at [capoff[b], capoff[b+1])
-};
-
-// Candidate table of a home cell in LDS. Pieces are runs of consecutive cells
-// of the cell's stencil, flattened into one candidate range [0, pref[n]).
-//   rec[r]  = (j offset = start - pref, sx, sy, zo): candidate g of piece r is
-//             point g + off, shifted into the home cell's frame by
-//             (sx, sy, (izf + zo) h), izf = the candidate's cell z index;
-//   code[r] = ((ox+k)(2k+1) + (oy+k))(2k+1) + k | wrap << 16, wrap = the
-//             periodic shift signs (+1) of x, y, z in 2-bit fields.
-struct Pieces {
-    float4* rec;
-    int* pref;
-    int* code;
-    int* n;
-};
-
-__host__ __device__ inline size_t pieces_lds_bytes(int npmax) {
-    size_t b = sizeof(float4) * (size_t)npmax + sizeof(int) * (size_t)(2 * npmax + 1) + sizeof(int) * 4;
-    return (b + 15) / 16 * 16;
-}
-
-__device__ inline Pieces pieces_view(unsigned char* base, int npmax) {
-    Pieces w;
-    w.rec = reinterpret_cast<float4*>(base);
-    w.pref = reinterpret_cast<int*>(w.rec + npmax);
-    w.code = w.pref + npmax + 1;
-    w.n = w.code + npmax;
-    return w;
-}
-
-__device__ inline double wrap_shift(int bits, int axis, double L) {
-    return (double)(((bits >> (2 * axis)) & 3) - 1) * L;
-}
 
 // Exact FP64 bin of a pair (the reference evaluation: r^2 = dx*dx + dy*dy +
 // dz*dz in that order, no fused multiply-add), -1 outside the shells or at
@@ -123,115 +63,6 @@ __device__ __noinline__ int exact_bin_t(const double4 P, const double4 Q, int wb
     int b = 0;
     while (b + 1 < nb && r2 >= e2[b + 1]) ++b;
     return b;
-}
-
-// Builds the flattened candidate ranges of the primary in cell (cx,cy,cz).
-// Every stencil run (fixed ox, oy; oz in [oz_lo, oz_hi]) becomes at most two
-// pieces of consecutive cells: the part that wraps through the z boundary and
-// the part that does not.
-__device__ void build_pieces(Pieces& W, const BinArgs& a, int cat, int cx, int cy, int cz) {
-    const int lane = lane_id();
-    const int nc = a.g.nc, k = a.g.k, K2 = 2 * k + 1;
-    const int base = cat * a.g.ncell;
-    int total_pieces = 0;
-    for (int r0 = 0; r0 < a.nruns; r0 += 64) {
-        const int r = r0 + lane;
-        int s0 = 0, e0 = 0, s1 = 0, e1 = 0, c0 = 0, c1 = 0;
-        float zo0 = 0.f, zo1 = 0.f, sx = 0.f, sy = 0.f;
-        bool has_wrap = false, has_in = false;
-        if (r < a.nruns) {
-            const StencilRun st = a.runs[r];
-            int qx = cx + st.ox, qy = cy + st.oy;
-            int wx = 0, wy = 0;
-            if (qx < 0) { qx += nc; wx = -1; } else if (qx >= nc) { qx -= nc; wx = 1; }
-            if (qy < 0) { qy += nc; wy = -1; } else if (qy >= nc) { qy -= nc; wy = 1; }
-            const int col = base + (qx * nc + qy) * nc;
-            const int zlo = cz + st.oz_lo, zhi = cz + st.oz_hi;
-            const int cbk = ((st.ox + k) * K2 + (st.oy + k)) * K2 + k;
-            const int wxy = (wx + 1) | ((wy + 1) << 2);
-            sx = (float)(st.ox * a.g.h);
-            sy = (float)(st.oy * a.g.h);
-            if (zlo < 0) {
-                // cells zlo..min(zhi,-1) are nc+zlo..nc+min(zhi,-1); z offset = izf - nc - cz
-                const int za = zlo + nc, zb = min(zhi, -1) + nc;
-                s0 = a.cell_start[col + za];
-                e0 = a.cell_start[col + zb + 1];
-                zo0 = (float)(-nc - cz);
-                c0 = cbk | ((wxy | (0 << 4)) << 16);
-                has_wrap = true;
-            } else if (zhi > nc - 1) {
-                // cells max(zlo,nc)..zhi are those minus nc; z offset = izf + nc - cz
-                const int za = max(zlo, nc) - nc, zb = zhi - nc;
-                s0 = a.cell_start[col + za];
-                e0 = a.cell_start[col + zb + 1];
-                zo0 = (float)(nc - cz);
-                c0 = cbk | ((wxy | (2 << 4)) << 16);
-                has_wrap = true;
-            }
-            const int lo_in = max(zlo, 0), hi_in = min(zhi, nc - 1);
-            if (hi_in >= lo_in) {
-                s1 = a.cell_start[col + lo_in];
-                e1 = a.cell_start[col + hi_in + 1];
-                zo1 = (float)(-cz);
-                c1 = cbk | ((wxy | (1 << 4)) << 16);
-                has_in = true;
-            }
-        }
-        const int np = (int)has_wrap + (int)has_in;
-        int incl = np;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += t;
-        }
-        int q = total_pieces + incl - np;
-        if (has_wrap) {
-            W.rec[q] = make_float4(__int_as_float(s0), sx, sy, zo0);
-            W.pref[q] = e0 - s0;
-            W.code[q] = c0;
-            ++q;
-        }
-        if (has_in) {
-            W.rec[q] = make_float4(__int_as_float(s1), sx, sy, zo1);
-            W.pref[q] = e1 - s1;
-            W.code[q] = c1;
-        }
-        total_pieces += __shfl(incl, 63, 64);
-    }
-    wave_sync();
-    // exclusive prefix of the piece lengths (held in pref) -> pref, and the
-    // point offset off = start - pref into rec.x
-    int carry = 0;
-    for (int q0 = 0; q0 < total_pieces; q0 += 64) {
-        const int q = q0 + lane;
-        const int len = q < total_pieces ? W.pref[q] : 0;
-        int incl = len;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += t;
-        }
-        wave_sync();
-        if (q < total_pieces) {
-            const int pr = carry + incl - len;
-            W.pref[q] = pr;
-            W.rec[q].x = __int_as_float(__float_as_int(W.rec[q].x) - pr);
-        }
-        carry += __shfl(incl, 63, 64);
-        wave_sync();
-    }
-    if (lane == 0) {
-        W.pref[total_pieces] = carry;
-        *W.n = total_pieces;
-    }
-    wave_sync();
-}
-
-// Wrap signs (+1, 2 bits per axis) of stencil offset `code` seen from cell
-// (cx, cy, cz): -1 where the neighbour cell index wrapped below 0, +1 above nc-1.
-__device__ inline int wrap_bits_of(int code, int cx, int cy, int cz, int k, int nc) {
-    const int K2 = 2 * k + 1;
-    const int ox = code / (K2 * K2) - k, oy = (code / K2) % K2 - k, oz = code % K2 - k;
-    auto w = [&](int c, int o) { const int q = c + o; return q < 0 ? 0 : (q >= nc ? 2 : 1); };
-    return w(cx, ox) | (w(cy, oy) << 2) | (w(cz, oz) << 4);
 }
 
 // Exact bin of the pair (primary p, candidate with list entry `entry`) for a

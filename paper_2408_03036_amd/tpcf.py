@@ -34,7 +34,7 @@ F_PAPER_LITERAL = 2
 EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
-           "tpcf_stage_times"]
+           "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles"]
 
 
 class TpcfError(RuntimeError):
@@ -91,6 +91,10 @@ def load():
     lib.tpcf_set_timing.restype = st
     lib.tpcf_stage_times.argtypes = [vp, i32, vp, vp]
     lib.tpcf_stage_times.restype = st
+    lib.tpcf_xi_count.argtypes = [vp, i32, vp]
+    lib.tpcf_xi_count.restype = st
+    lib.tpcf_xi_multipoles.argtypes = [vp, i32, vp, i64, i32, vp, vp]
+    lib.tpcf_xi_multipoles.restype = st
     _lib = lib
     return lib
 
@@ -212,6 +216,26 @@ class Handle:
                                              _ptr(out)))
         return out
 
+    # -- anisotropic 2PCF (Sec. 4.1) ----------------------------------
+    def xi_count(self, nmu, out=None):
+        """DD(r, mu) of the catalogue given to build_grid: int64 [nbins][nmu]."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nbins, int(nmu)), dtype=torch.int64, device=f"cuda:{self.device}")
+        _check_dev(out, torch.int64, "out")
+        self._chk(self.lib.tpcf_xi_count(self.h, int(nmu), _ptr(out)))
+        return out
+
+    def xi_multipoles(self, counts, n_data, ells):
+        """xi_l(r_b) of the natural estimator from DD(r, mu): float64 [len(ells)][nbins]."""
+        import torch
+        _check_dev(counts, torch.int64, "counts")
+        el = np.ascontiguousarray(np.array(ells, dtype=np.int32).reshape(-1))
+        out = torch.empty((el.shape[0], self.nbins), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._chk(self.lib.tpcf_xi_multipoles(self.h, int(counts.shape[1]), _ptr(counts), int(n_data),
+                                              el.shape[0], ctypes.c_void_p(el.ctypes.data), _ptr(out)))
+        return out
+
     def sync(self):
         self._chk(self.lib.tpcf_sync(self.h))
 
@@ -229,9 +253,11 @@ class Handle:
         self._chk(self.lib.tpcf_set_timing(self.h, 1 if enable else 0))
 
     def stage_times(self):
-        ms = np.zeros(5)
-        nl = np.zeros(5, dtype=np.int64)
-        self._chk(self.lib.tpcf_stage_times(self.h, 5, ctypes.c_void_p(ms.ctypes.data),
+        """Milliseconds and launches per stage: grid, binning, harmonics,
+        contraction, finalisation, 2PCF counts."""
+        ms = np.zeros(6)
+        nl = np.zeros(6, dtype=np.int64)
+        self._chk(self.lib.tpcf_stage_times(self.h, 6, ctypes.c_void_p(ms.ctypes.data),
                                             ctypes.c_void_p(nl.ctypes.data)))
         return ms, nl
 

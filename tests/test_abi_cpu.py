@@ -86,6 +86,8 @@ def test_null_arguments(lib):
     assert lib.tpcf_alm_accumulate(None) == T.TPCF_ERR_ARG
     assert lib.tpcf_sync(None) == T.TPCF_ERR_ARG
     assert lib.tpcf_rebinned_count(None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_xi_count(None, 10, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_xi_multipoles(None, 10, None, 10, 1, None, None) == T.TPCF_ERR_ARG
     assert b"invalid" in lib.tpcf_last_error(None)
     lib.tpcf_destroy(None)
 
