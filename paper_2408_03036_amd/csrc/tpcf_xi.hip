@@ -39,9 +39,9 @@ namespace {
 
 constexpr int kXW = 4;                     // wavefronts per workgroup
 constexpr int kXG = kItemPrims / kXW;      // primaries per wavefront
-constexpr int kXTile = 512;                // candidates per LDS tile
+constexpr int kXTile = 128;                // candidates per LDS tile
 constexpr int kXUT = kXTile / 64;          // tile candidates per lane
-constexpr int kXStage = kXTile / (64 * kXW);
+constexpr int kXStage = (kXTile + 64 * kXW - 1) / (64 * kXW);  // candidates each thread stages
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 32;           // ints between queue cursors (128 bytes)
 static_assert(kXG * kXW == kItemPrims, "item size");
@@ -233,13 +233,18 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
             }
         }
 
+        // thread x stages tile slots x, x + 256, ... below kXTile
         XStaged st[kXStage];
+        const bool stager = (int)threadIdx.x < kXTile;
 #pragma unroll
         for (int s = 0; s < kXStage; ++s) {
             st[s].r = 0;
+            st[s].ok = false;
             const int i = s * 64 * kXW + threadIdx.x;
-            xstage_load(st[s], S, total, i, a.pf);
-            xstage_store<SINGLE>(st[s], tiles + i, tent + i, cshift, a.g.hf);
+            if (i < kXTile) {
+                xstage_load(st[s], S, total, i, a.pf);
+                xstage_store<SINGLE>(st[s], tiles + i, tent + i, cshift, a.g.hf);
+            }
         }
         __syncthreads();
         int buf = 0;
@@ -247,10 +252,11 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
             const float4* cur = tiles + buf * kXTile;
             const uint32_t* cure = tent + buf * kXTile;
             const bool more = t + kXTile < total;
-            if (more) {
+            if (more && stager) {
 #pragma unroll
                 for (int s = 0; s < kXStage; ++s)
-                    xstage_load(st[s], S, total, t + kXTile + s * 64 * kXW + (int)threadIdx.x, a.pf);
+                    if (s * 64 * kXW + (int)threadIdx.x < kXTile)
+                        xstage_load(st[s], S, total, t + kXTile + s * 64 * kXW + (int)threadIdx.x, a.pf);
             }
             const int nt = min(kXTile, total - t);
 #pragma unroll 2
@@ -315,11 +321,13 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
                     }
                 }
             }
-            if (more) {
+            if (more && stager) {
 #pragma unroll
                 for (int s = 0; s < kXStage; ++s)
-                    xstage_store<SINGLE>(st[s], tiles + (buf ^ 1) * kXTile + s * 64 * kXW + threadIdx.x,
-                                         tent + (buf ^ 1) * kXTile + s * 64 * kXW + threadIdx.x, cshift, a.g.hf);
+                    if (s * 64 * kXW + (int)threadIdx.x < kXTile)
+                        xstage_store<SINGLE>(st[s], tiles + (buf ^ 1) * kXTile + s * 64 * kXW + threadIdx.x,
+                                             tent + (buf ^ 1) * kXTile + s * 64 * kXW + threadIdx.x, cshift,
+                                             a.g.hf);
             }
             __syncthreads();
             buf ^= 1;
