@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--refine", type=int, default=0)
     ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi"],
                     help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF")
+    ap.add_argument("--isotropic", action="store_true",
+                    help="3pcf: the isotropic schedule, multipoles (l, l, 0) only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -256,6 +258,10 @@ def main():
     edges = np.linspace(20.0, 120.0, 11)
     lmax, Lmax = 10, 2
     mults = all_multipoles(lmax, Lmax)
+    flags = 0
+    if args.isotropic:
+        mults = [(l, l, 0) for l in range(lmax + 1)]
+        flags = T.F_ISOTROPIC
     print(f"[bench] generating {args.ncat} catalogues on the GPU", file=sys.stderr, flush=True)
     sizes, pos = make_batch(torch, args.ncat, 50_000, 300_000, box, sigma, fgrowth, grid, dev)
     ntot = int(sizes.sum())
@@ -264,7 +270,7 @@ def main():
 
     print(f"[bench] {args.precision}: {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
-    h = T.Handle(box, edges, lmax, precision=prec_id, grid_refine=args.refine,
+    h = T.Handle(box, edges, lmax, precision=prec_id, flags=flags, grid_refine=args.refine,
                  workspace_limit=96 << 30)
     h.set_timing(True)
     dt, ms, nl, npairs, out = time_steps(torch, h, sizes, pos, mults, args.steps, args.warmup)
@@ -298,11 +304,20 @@ def main():
                    "mfma_products_per_fp32_product": mfma_mult}
     if prec_id in (T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6) and stages["contract_ms"] > 0:
         contraction["frac_bf16_peak"] = cflop * mfma_mult / (stages["contract_ms"] / 1e3) / PEAK_BF16_MFMA
+    if args.isotropic:
+        # only the l1 = l2 blocks, on FP64 MFMA: sum over catalogues, (l, m) and parts of 2 P nb^2
+        nb = len(edges) - 1
+        iflop = sum(2.0 * nb * nb * float(P) * (1 if m == 0 else 2)
+                    for P in sizes for m in range(lmax + 1) for _ in range(m, lmax + 1))
+        contraction = {"schedule": "isotropic (l1 = l2 blocks, FP64 MFMA)", "flop": iflop,
+                       "ms": stages["contract_ms"],
+                       "frac_fp64_mfma_peak": iflop / (stages["contract_ms"] / 1e3) / 78.6e12
+                       if stages["contract_ms"] > 0 else None}
 
     fp64 = None
     if not args.no_fp64 and prec_id != T.PREC_FP64:
         print("[bench] fp64 comparison", file=sys.stderr, flush=True)
-        h = T.Handle(box, edges, lmax, precision=T.PREC_FP64, grid_refine=args.refine,
+        h = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=flags, grid_refine=args.refine,
                      workspace_limit=96 << 30)
         h.set_timing(True)
         dt64, ms64, nl64, np64, out64 = time_steps(torch, h, sizes, pos, mults, max(2, args.steps // 2), 1)
@@ -330,7 +345,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batched covariance run: {args.ncat} Zel'dovich+RSD catalogues, "
                                f"sizes log-uniform [5e4,3e5] ({ntot} points), 1000 Mpc/h boxes, "
-                               f"10 bins [20,120] Mpc/h, lmax 10, L<=2 ({len(mults)} multipoles)",
+                               f"10 bins [20,120] Mpc/h, lmax 10, "
+                               + (f"isotropic schedule ({len(mults)} multipoles (l,l,0))" if args.isotropic
+                                  else f"L<=2 ({len(mults)} multipoles)"),
                    "precision": args.precision, "ncat": args.ncat, "points": ntot,
                    "pairs_per_step": int(npairs), "parallelism": "single GPU"},
         "catalogs_per_hour": cats_per_hour,

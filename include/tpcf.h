@@ -83,9 +83,16 @@ typedef enum {
 
 enum {
     TPCF_F_KEEP_DEGENERATE = 1u, /* keep j == k terms (default: distinct triplets only)     */
-    TPCF_F_PAPER_LITERAL = 2u    /* output eq. (slep2sugy) exactly as printed, applied to the
+    TPCF_F_PAPER_LITERAL = 2u,   /* output eq. (slep2sugy) exactly as printed, applied to the
                                     orthonormal-Y coefficients (4 pi)^2 NNN^m / RRR; equals the
                                     default output times 4 pi / sqrt((2l1+1)(2l2+1))          */
+    TPCF_F_ISOTROPIC = 4u        /* isotropic schedule (the L = 0 case of eq. (TripoSH), Sec.
+                                    2.3): the contraction forms only the l1 = l2 blocks of NNN^m,
+                                    in FP64 (MFMA) from the pair pass of the chosen precision,
+                                    and tpcf_multipoles / tpcf_run_catalogs accept only (l, l, 0)
+                                    triples. By the addition theorem zeta_{l l 0}(r1, r2) is then
+                                    the Legendre coefficient zeta_l of zeta(r1, r2, cos theta_12).
+                                    Exported NNN^m is zero off the l1 = l2 blocks. nbins <= 32. */
 };
 
 typedef struct {

@@ -755,7 +755,14 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     c.mode = (h->mode == TPCF_PREC_MIXED_BF16X3 && !h->unit_w) ? TPCF_PREC_MIXED_BF16X6 : h->mode;
     c.unit_weights = h->unit_w ? 1 : 0;
     c.pw = P<float>(h->d_pw);
-    HIPCHK(launch_contract(c, h->stream));
+    if (h->cfg.flags & TPCF_F_ISOTROPIC) {
+        // only the l1 = l2 blocks are formed; the rest of the partials is zero
+        HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(P<double>(h->d_part) + (int64_t)ch.sub_begin * h->gsize),
+                               (int64_t)nsub * h->gsize, 0ull, h->stream));
+        HIPCHK(launch_contract_iso(c, h->stream));
+    } else {
+        HIPCHK(launch_contract(c, h->stream));
+    }
     SelfArgs s{};
     s.A = h->d_A.p;
     s.ldA = h->ldA;
@@ -797,6 +804,8 @@ tpcf_status check_mults(tpcf_handle h, int32_t n_mult, const int32_t* m) {
             L > l1 + l2 || ((l1 + l2 + L) & 1))
             return fail(h, TPCF_ERR_ARG, "invalid multipole triple (" + std::to_string(l1) + "," +
                                              std::to_string(l2) + "," + std::to_string(L) + ")");
+        if ((h->cfg.flags & TPCF_F_ISOTROPIC) && L != 0)
+            return fail(h, TPCF_ERR_ARG, "an isotropic handle gives only (l, l, 0) multipoles");
     }
     return TPCF_OK;
 }
@@ -877,7 +886,8 @@ tpcf_status validate_config(const tpcf_config* c) {
     if (c->precision < 0 || c->precision > 3) return TPCF_ERR_ARG;
     if (c->grid_refine < 0 || c->grid_refine > 4) return TPCF_ERR_RANGE;
     if (c->workspace_limit < 0) return TPCF_ERR_ARG;
-    if (c->flags & ~(uint32_t)(TPCF_F_KEEP_DEGENERATE | TPCF_F_PAPER_LITERAL)) return TPCF_ERR_ARG;
+    if (c->flags & ~(uint32_t)(TPCF_F_KEEP_DEGENERATE | TPCF_F_PAPER_LITERAL | TPCF_F_ISOTROPIC))
+        return TPCF_ERR_ARG;
     const int mode = c->precision;
     if (contract_lds_bytes(mode, c->nbins, c->lmax) > 160 * 1024) return TPCF_ERR_RANGE;
     if (mode == TPCF_PREC_MIXED_BF16X3 &&
@@ -1023,6 +1033,7 @@ tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out) {
         a.scale = P<double>(h->d_scale);
         a.gaunt = P<double>(h->d_gaunt);
         a.subtract_self = (h->cfg.flags & TPCF_F_KEEP_DEGENERATE) ? 0 : 1;
+        a.isotropic = (h->cfg.flags & TPCF_F_ISOTROPIC) ? 1 : 0;
         a.out = d_nnn_out;
         HIPCHK(launch_export_nnn(a, h->stream));
     }

@@ -240,6 +240,163 @@ __global__ void __launch_bounds__(256) k_contract(ContractArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- isotropic schedule
+// The isotropic multipoles are the L = 0 case of eq. (slep2sugy) (Sec. 2.3:
+// the tripolar basis with L = 0 reduces to Legendre polynomials of the angle
+// between r1 and r2), and they read only the l1 = l2 blocks of G_m:
+//   G_m[(b1,l),(b2,l)] = sum_p w_p Re(A_lm(p,b1) conj(A_lm(p,b2))).
+// One wavefront per (subchunk, (l, m)) forms that nb x nb block on 16x16x4
+// MFMA in 16 x 16 tiles over (b1, b2) (up to 32 bins). A step covers 64
+// primaries from a 16-aligned start: lane (i, g) = (lane % 16, lane / 16)
+// loads 16 consecutive values of bin i (vector loads, masked to the subchunk)
+// and feeds 16 MFMAs, each summing four primaries, one per lane group. FP64
+// operands use FP64 MFMA; FP32 operands use FP32 MFMA, and the FP32 sums of
+// one step (16 products per entry and chain) go into FP64 registers.
+constexpr int kIsoWaves = 4;
+
+// 16 consecutive values of one row (16-aligned), kept in their storage type
+// until used: the next step's values are loaded while the current step's
+// MFMAs run.
+template <typename TA> struct Raw16;
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <> struct Raw16<float> {
+    fvec4 v[4];
+    __device__ __forceinline__ void load(const float* src) {
+        const fvec4* p = reinterpret_cast<const fvec4*>(src);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = p[q];
+    }
+    __device__ __forceinline__ double get(int k) const { return (double)v[k >> 2][k & 3]; }
+};
+template <> struct Raw16<double> {
+    double2 v[8];
+    __device__ __forceinline__ void load(const double* src) {
+        const double2* p = reinterpret_cast<const double2*>(src);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = p[q];
+    }
+    __device__ __forceinline__ double get(int k) const { return (k & 1) ? v[k >> 1].y : v[k >> 1].x; }
+};
+
+template <typename TA, bool W>
+__global__ void __launch_bounds__(64 * kIsoWaves) k_contract_iso(ContractArgs a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lmax = a.lmax, nb = a.nb;
+    int u = blockIdx.y * kIsoWaves + wave;
+    const int nlm = (lmax + 1) * (lmax + 2) / 2;
+    if (u >= nlm) return;
+    int m = 0;
+    while (u >= lmax - m + 1) {  // units ordered m-major, l = m..lmax
+        u -= lmax - m + 1;
+        ++m;
+    }
+    const int l = m + u;
+    const int nl = lmax - m + 1, K = nb * nl;
+    const int parts = m == 0 ? 1 : 2;
+    const int NV = n_values(lmax);
+    const int v0 = value_offset(lmax, m) + (l - m);
+    const int s = blockIdx.x;
+    const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
+    const int i = lane & 15, g = lane >> 4;
+    const int nt = (nb + 15) / 16;  // 1 or 2 tiles of bins
+    const TA* A = reinterpret_cast<const TA*>(a.A);
+    // rows of bins i and 16 + i (clamped in range; their values are zeroed)
+    const bool ok0 = i < nb, ok1 = nt > 1 && 16 + i < nb;
+    const int64_t row0 = ((int64_t)min(i, nb - 1) * NV + v0) * a.ldA;
+    const int64_t row1 = ((int64_t)min(16 + i, nb - 1) * NV + v0) * a.ldA;
+    const int64_t pstep = (int64_t)nl * a.ldA;  // re -> im rows
+    f64x4 acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = (f64x4)0.0;
+
+    // steps of 64 primaries from a 16-aligned start; rows are padded to ldA
+    // (a multiple of 64), so every 16-aligned group starting below pb is
+    // inside its row
+    const int64_t p00 = pa & ~(int64_t)15;
+    const int nsteps = (int)((pb - p00 + 63) / 64);
+    const int nit = nsteps * parts;
+    auto group = [&](int it) { return p00 + (int64_t)(it / parts) * 64 + 16 * g; };
+    auto fetch = [&](int it, Raw16<TA>& r0, Raw16<TA>& r1) {
+        const int64_t q0 = group(it);
+        if (q0 < pb) {
+            const int64_t off = (it % parts) * pstep + q0;
+            r0.load(A + row0 + off);
+            if (nt > 1) r1.load(A + row1 + off);
+        }
+    };
+    Raw16<TA> c0, c1, n0, n1;
+    if (nit > 0) fetch(0, n0, n1);
+    // FP32 operands: FP32 16x16x4 MFMA in two chains, emptied into FP64
+    // after every step of 64 primaries (16 products per chain and entry)
+    constexpr bool F32 = std::is_same<TA, float>::value;
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    double accd[3][4];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accd[q][r] = 0.0;
+    for (int it = 0; it < nit; ++it) {
+        c0 = n0;
+        c1 = n1;
+        if (it + 1 < nit) fetch(it + 1, n0, n1);
+        const int64_t q0 = group(it);
+        const int lo = (int)max<int64_t>(pa - q0, -1), hi = (int)min<int64_t>(pb - q0, 17);
+        if constexpr (F32) {
+            f32x4 sa[3], sb[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sa[q] = sb[q] = (f32x4)0.0f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const bool in = k >= lo && k < hi;
+                const float x0 = (in && ok0) ? c0.v[k >> 2][k & 3] : 0.0f;
+                const float wk = W ? (in ? (float)a.pw[a.p_begin + q0 + k] : 0.0f) : 1.0f;
+                const float wa0 = W ? x0 * wk : x0;
+                f32x4* acc = (k & 1) ? sb : sa;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa0, x0, acc[0], 0, 0, 0);
+                if (nt > 1) {
+                    const float x1 = (in && ok1) ? c1.v[k >> 2][k & 3] : 0.0f;
+                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa0, x1, acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(W ? x1 * wk : x1, x1, acc[2], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) accd[q][r] += (double)sa[q][r] + (double)sb[q][r];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const bool in = k >= lo && k < hi;
+                const double x0 = (in && ok0) ? c0.get(k) : 0.0;
+                const double wk = W ? (in ? a.pd[a.p_begin + q0 + k].w : 0.0) : 1.0;
+                const double wa0 = W ? x0 * wk : x0;
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa0, x0, acc[0], 0, 0, 0);
+                if (nt > 1) {
+                    const double x1 = (in && ok1) ? c1.get(k) : 0.0;
+                    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa0, x1, acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(W ? x1 * wk : x1, x1, acc[2], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // upper triangle of the block: tiles (0,0), (0,1), (1,1)
+    const int64_t base = (int64_t)(a.sub_base + s) * a.gsize + a.goff[m];
+    const int j = lane & 15;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (q > 0 && nt < 2) break;
+        const int ti = q == 2 ? 1 : 0, tj = q == 0 ? 0 : 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // output rows of a 16x16 MFMA: FP64 lane / 16 + 4 r, FP32 4 (lane / 16) + r
+            const int c1r = 16 * ti + (F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r), c2 = 16 * tj + j;
+            if (c1r < nb && c2 < nb && c1r <= c2)
+                a.part64[base + (int64_t)(c1r * nl + (l - m)) * K + c2 * nl + (l - m)] =
+                    F32 ? accd[q][r] : acc[q][r];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- split-BF16 contraction
 // Eight wavefronts per workgroup, up to two 32x32 output tiles each. Per step
 // (KS primaries of one part), every thread stages 8 consecutive primaries of
@@ -606,7 +763,7 @@ __global__ void k_export_nnn(NnnArgs a) {
     const int64_t t = idx / ((int64_t)nb * nb);
     const int l2 = (int)(t % s1), l1 = (int)((t / s1) % s1), m = (int)(t / ((int64_t)s1 * s1));
     double v = 0.0;
-    if (l1 >= m && l2 >= m) {
+    if (l1 >= m && l2 >= m && (!a.isotropic || l1 == l2)) {
         const int nl = a.lmax - m + 1, K = nb * nl;
         const int ci = b1 * nl + (l1 - m), cj = b2 * nl + (l2 - m);
         v = a.scale[l1 * s1 + m] * a.scale[l2 * s1 + m] *
@@ -719,6 +876,22 @@ hipError_t launch_contract_bf16_w(const ContractArgs& a, hipStream_t s) {
 template <int NPC>
 hipError_t launch_contract_bf16(const ContractArgs& a, hipStream_t s) {
     return a.unit_weights ? launch_contract_bf16_w<NPC, false>(a, s) : launch_contract_bf16_w<NPC, true>(a, s);
+}
+
+hipError_t launch_contract_iso(const ContractArgs& a, hipStream_t s) {
+    if (a.nsub <= 0) return hipSuccess;
+    if (a.nb > 32) return hipErrorInvalidValue;
+    const int nlm = (a.lmax + 1) * (a.lmax + 2) / 2;
+    const dim3 grid(a.nsub, (nlm + kIsoWaves - 1) / kIsoWaves);
+    const bool f64 = a.mode == 0;
+    if (a.unit_weights) {
+        if (f64) hipLaunchKernelGGL((k_contract_iso<double, false>), grid, dim3(64 * kIsoWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_contract_iso<float, false>), grid, dim3(64 * kIsoWaves), 0, s, a);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_contract_iso<double, true>), grid, dim3(64 * kIsoWaves), 0, s, a);
+        else hipLaunchKernelGGL((k_contract_iso<float, true>), grid, dim3(64 * kIsoWaves), 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s) {

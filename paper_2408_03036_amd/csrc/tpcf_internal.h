@@ -194,6 +194,9 @@ struct ContractArgs {
     const float* pw;         // FP32 weights, sorted order (split-BF16 modes)
 };
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s);
+// Isotropic schedule: only the l1 = l2 blocks of every G_m (nb <= 32); the
+// other entries of the partials must be zero beforehand.
+hipError_t launch_contract_iso(const ContractArgs& a, hipStream_t s);
 
 struct SelfArgs {
     const void* A;
@@ -241,6 +244,7 @@ struct NnnArgs {
     const double* scale;     // [(lmax+1)^2] s_lm at l*(lmax+1)+m
     const double* gaunt;     // [(lmax+1)^3 (2lmax+1)] g_L(l1,l2,m) * gamma0_L at ((m*s1+l1)*s1+l2)*(2lmax+1)+L
     int subtract_self;
+    int isotropic;           // only l1 = l2 blocks exist (others are exported as zero)
     double* out;             // [(lmax+1)^3][nb][nb]
 };
 hipError_t launch_export_nnn(const NnnArgs& a, hipStream_t s);

@@ -30,6 +30,7 @@ PREC_MIXED_BF16X3 = 2
 PREC_MIXED_BF16X6 = 3
 F_KEEP_DEGENERATE = 1
 F_PAPER_LITERAL = 2
+F_ISOTROPIC = 4
 
 EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",

@@ -164,3 +164,34 @@ def test_batched_64_catalogues(torch):
     err = alm_slice_error(torch, pos0, box, edges, lmax, T.PREC_FP64, 1000)
     say(f"  catalogue 0 a_lm slice rel err {err:.3e}")
     assert err < 1e-12
+
+
+def test_isotropic_batch(torch):
+    """The benchmark's batch on the isotropic schedule (FP32 pair pass, l1 = l2
+    blocks only) against the (l, l, 0) rows of the full FP64 run."""
+    box, edges, lmax = 1000.0, np.linspace(20.0, 120.0, 11), 10
+    mults = O.all_multipoles(lmax, 2)
+    iso = [(l, l, 0) for l in range(lmax + 1)]
+    rows = [mults.index(t) for t in iso]
+    sizes = C.log_uniform_sizes(64, 50_000, 300_000, C.BASE_SEED + 777)
+    say(f"  generating 64 catalogues ({int(sizes.sum())} points)")
+    P = torch.cat([C.zeldovich_torch(int(n), box, 6.0, 0.8, C.catalogue_seed(i), grid=256, device="cuda")
+                   for i, n in enumerate(sizes)], dim=0).contiguous()
+
+    def batch(prec, flags, ms):
+        h = T.Handle(box, edges, lmax, precision=prec, flags=flags, workspace_limit=96 << 30)
+        out = h.run_catalogs(sizes, sizes, P, None, ms)
+        h.sync()
+        n = h.pair_count()
+        h.close()
+        return out.cpu().numpy(), n
+
+    say("  batched isotropic (FP32 pair pass)")
+    got, n_iso = batch(T.PREC_MIXED_BF16X3, T.F_ISOTROPIC, iso)
+    say("  batched FP64, all multipoles")
+    ref, n_ref = batch(T.PREC_FP64, 0, mults)
+    assert n_iso == n_ref
+    ref = ref[:, rows]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"  isotropic vs FP64 rel err {err:.3e}")
+    assert err < 1e-5

@@ -289,3 +289,69 @@ def test_workspace_limit_enforced(torch):
         h.alm_accumulate()
     assert e.value.status == T.TPCF_ERR_ALLOC
     h.close()
+
+
+# ------------------------------------------------------------------ isotropic schedule
+
+
+def iso_rows(mults, lmax):
+    """Indices of the (l, l, 0) triples in mults, l = 0..lmax."""
+    idx = {tuple(t): i for i, t in enumerate(mults)}
+    return [idx[(l, l, 0)] for l in range(lmax + 1)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_isotropic_matches_oracle(torch, dense_case, prec):
+    """TPCF_F_ISOTROPIC forms only the l1 = l2 blocks (FP64 MFMA); its (l, l, 0)
+    outputs, the Legendre coefficients zeta_l(r1, r2), match the oracle within
+    1e-12 (FP64 pair pass) or 1e-5 (FP32 pair pass)."""
+    pos, mults, ref, res = dense_case
+    lmax = DENSE["lmax"]
+    iso = [(l, l, 0) for l in range(lmax + 1)]
+    got, npairs, _, nnn = run_gpu(torch, pos, DENSE["box"], DENSE["edges"], lmax, iso, prec,
+                                  flags=T.F_ISOTROPIC, want_nnn=True)
+    assert npairs == res.npairs
+    r = ref[iso_rows(mults, lmax)]
+    err = rel_err(got, r)
+    say(f"  isotropic {PNAME[prec]} rel err {err:.3e}")
+    assert err < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+    # exported NNN^m: zero off the l1 = l2 blocks, the oracle's on them
+    s1 = lmax + 1
+    off = np.ones((s1, s1), dtype=bool)
+    np.fill_diagonal(off, False)
+    assert np.all(nnn[:, off] == 0.0)
+    diag = np.array([nnn[m, l, l] for m in range(s1) for l in range(m, s1)])
+    rdiag = np.array([res.nnn[m, l, l].real for m in range(s1) for l in range(m, s1)])
+    derr = float(np.abs(diag - rdiag).max() / np.abs(rdiag).max())
+    assert derr < (1e-12 if prec == T.PREC_FP64 else 1e-5), derr
+
+
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
+def test_isotropic_weighted_and_wide(torch, prec):
+    """Data minus randoms weights, and 20 bins (two 16-bin tiles of the block)."""
+    box, nd = 300.0, 3000
+    edges = np.linspace(4.0, 64.0, 21)
+    lmax = 4
+    D = C.zeldovich(nd, box, 4.0, 0.8, C.catalogue_seed(70), grid=64)
+    pos = np.vstack([D, C.randoms(2 * nd, box, C.randoms_seed(70))])
+    w = C.dr_weights(nd, 2 * nd)
+    iso = [(l, l, 0) for l in range(lmax + 1)]
+    say("  oracle: weighted isotropic case")
+    ref, _, res = O.run(pos, box, edges, lmax, iso, w=w, n_data=nd)
+    got, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, iso, prec, w=w, n_data=nd,
+                                flags=T.F_ISOTROPIC)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  isotropic weighted {PNAME[prec]} rel err {err:.3e}")
+    assert err < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+
+
+def test_isotropic_rejects_anisotropic_triples(torch):
+    h = T.Handle(200.0, np.linspace(0.0, 40.0, 9), 4, flags=T.F_ISOTROPIC)
+    h.build_grid(gpu(torch, C.poisson(500, 200.0, 3)))
+    h.alm_accumulate()
+    h.contract()
+    with pytest.raises(T.TpcfError) as e:
+        h.multipoles([(2, 0, 2)])
+    assert e.value.status == T.TPCF_ERR_ARG
+    h.close()
