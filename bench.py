@@ -226,6 +226,80 @@ def bench_xi(args):
     print(json.dumps(line))
 
 
+def bench_cov(args):
+    """Covariance step of Sec. 4.3 at the paper's size: 3000 mock data vectors of
+    336 entries (the joint 2PCF + 3PCF vector of its covariance figure), taken
+    by offset from rows of 400 values; covariance, then Hartlap precision."""
+    import torch
+    from paper_2408_03036_amd import tpcf as T
+
+    nm, stride, nd = 3000, 400, 336
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(2408030360)
+    # correlated Gaussian mock vectors (stand-ins for the measured multipoles)
+    Lmix = torch.randn((stride, stride), generator=g, device="cuda:0", dtype=torch.float64) * 0.05
+    Lmix += torch.eye(stride, device="cuda:0", dtype=torch.float64)
+    src = (torch.randn((nm, stride), generator=g, device="cuda:0", dtype=torch.float64) @ Lmix.T).contiguous()
+    off = np.sort(np.random.default_rng(2408030360).choice(stride, nd, replace=False)).astype(np.int64)
+    torch.cuda.synchronize()
+    h = T.Handle(100.0, np.linspace(0.0, 10.0, 2), 0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        mean, cov = h.covariance(src, offsets=off)
+        return cov, h.precision(cov, nm)
+
+    for _ in range(args.warmup):
+        step()
+    h.sync()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_cov = t_inv = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev[0].record(stream)
+        mean, cov = h.covariance(src, offsets=off)
+        ev[1].record(stream)
+        prec = h.precision(cov, nm)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_cov += ev[0].elapsed_time(ev[1])
+        t_inv += ev[1].elapsed_time(ev[2])
+    dt = (time.perf_counter() - t0) / args.steps
+    h.close()
+    t_cov /= args.steps
+    t_inv /= args.steps
+    # FP64 work: the covariance product (upper triangle, 2 flop per product) and the
+    # Gauss-Jordan sweep (2 n^3)
+    f_cov = float(nm) * nd * (nd + 1)
+    f_inv = 2.0 * nd ** 3
+    roof = {"kernel": "k_cov_syrk + k_cov_invert (FP64)", "bound": "mfma",
+            "achieved": (f_cov + f_inv) / ((t_cov + t_inv) / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": (f_cov + f_inv) / ((t_cov + t_inv) / 1e3) / 78.6e12, "traffic": None,
+            "covariance_ms": t_cov, "precision_ms": t_inv}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cov_oracle as V
+        sub = src[:200].cpu().numpy()[:, off]
+        t0 = time.perf_counter()
+        V.covariance(sub)
+        t1 = time.perf_counter() - t0
+        cpu = {"value": 200 / t1, "unit": "data vectors/s", "cores": 1, "kind": "oracle",
+               "sample": f"covariance loops of the oracle over the first 200 mocks ({nd} entries) in {t1:.1f} s"}
+    line = {
+        "metric": "mock data vectors/s into covariance + Hartlap precision (Sec. 4.3), 1 GPU",
+        "value": nm / dt, "unit": "data vectors/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"covariance of {nm} mock data vectors of {nd} entries (offsets into rows of "
+                               f"{stride}), Hartlap-corrected precision matrix",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,8 +310,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--refine", type=int, default=0)
-    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi"],
-                    help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF")
+    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov"],
+                    help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF; "
+                         "cov: covariance and precision over mock data vectors")
     ap.add_argument("--isotropic", action="store_true",
                     help="3pcf: the isotropic schedule, multipoles (l, l, 0) only")
     args = ap.parse_args()
@@ -248,6 +323,9 @@ def main():
         sys.exit(2)
     if args.workload == "xi":
         bench_xi(args)
+        return
+    if args.workload == "cov":
+        bench_cov(args)
         return
 
     import torch

@@ -204,6 +204,53 @@ tpcf_status tpcf_xi_count(tpcf_handle h, int32_t nmu, int64_t* d_counts);
 tpcf_status tpcf_xi_multipoles(tpcf_handle h, int32_t nmu, const int64_t* d_counts, int64_t n_data,
                                int32_t n_ell, const int32_t* h_ells, double* d_out);
 
+/*
+ * Covariance step of Sec. 4.3, for measurements of a suite of mock catalogues.
+ *
+ * tpcf_triangle_index: host helper building a 3PCF data vector. For each
+ * multipole row t of h_rows (indices into an n_mult x nbins x nbins output
+ * block such as one catalogue of tpcf_run_catalogs) it lists the triangle
+ * configurations in the order of the flattened (r1, r2) grid: unique
+ * configurations r1 < r2 (bin centres), side difference r2 - r1 >= eta * dr and
+ * shortest side r1 >= r_min (Sec. 4.3 and 5). Bins must be of equal width dr.
+ *  h_offsets: capacity entries (t nbins + b1) nbins + b2; h_count: number of
+ *  configurations (also when capacity is 0, then h_offsets may be NULL).
+ *  Returns TPCF_ERR_RANGE when capacity (> 0) is too small or the bins are not
+ *  of equal width. Needs no handle and no device.
+ */
+tpcf_status tpcf_triangle_index(int32_t nbins, const double* h_edges, double eta, double r_min, int32_t n_rows,
+                                const int32_t* h_rows, int64_t capacity, int64_t* h_offsets, int64_t* h_count);
+
+/*
+ * Mean and unbiased covariance of n_mocks data vectors (eq. (covariance)):
+ *   C_ij = 1/(N_m - 1) sum_k (d_i^k - dbar_i)(d_j^k - dbar_j).
+ *  d_src    : device, n_mocks rows of `stride` float64 (for example the output
+ *             of tpcf_run_catalogs, stride = n_mult nbins nbins).
+ *  h_offsets: host, n_d offsets into a row giving the data vector (NULL: the
+ *             first n_d entries); each in 0 .. stride-1.
+ *  d_mean   : device, n_d float64, or NULL.  d_cov: device, n_d x n_d float64.
+ * FP64 throughout (the products on FP64 MFMA); the mean is summed in mock order.
+ */
+tpcf_status tpcf_covariance(tpcf_handle h, int32_t n_mocks, int64_t stride, const double* d_src, int32_t n_d,
+                            const int64_t* h_offsets, double* d_mean, double* d_cov);
+
+/*
+ * Precision matrix with the Hartlap correction (eq. (Hartlap)):
+ *   d_prec = (N_m - N_d - 2)/(N_m - 1) * inverse(d_cov),
+ * by a Gauss-Jordan sweep in FP64 (d_prec may equal d_cov: in place).
+ * n_d in 1 .. 4096 and n_mocks >= n_d + 3 (else TPCF_ERR_RANGE); a matrix that
+ * is not positive definite gives TPCF_ERR_RANGE. Synchronises the stream.
+ */
+tpcf_status tpcf_precision_matrix(tpcf_handle h, int32_t n_d, const double* d_cov, int32_t n_mocks, double* d_prec);
+
+/*
+ * Percival correction of the parameter variances (eqs. (Perc1), (Perc)):
+ *   m1 = (1 + B (N_d - N_p)) / (1 + A + B (N_p + 1)),
+ *   A = 2 / ((N_m - N_d - 1)(N_m - N_d - 4)),  B = (N_m - N_d - 2) / ((N_m - N_d - 1)(N_m - N_d - 4)).
+ * Requires n_mocks >= n_d + 5. Host only.
+ */
+tpcf_status tpcf_percival_m1(int32_t n_mocks, int32_t n_d, int32_t n_params, double* h_m1);
+
 /* Waits for all work enqueued by h. */
 tpcf_status tpcf_sync(tpcf_handle h);
 

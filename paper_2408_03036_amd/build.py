@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtpcf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["tpcf.cpp", "tpcf_grid.hip", "tpcf_pairs.hip", "tpcf_contract.hip", "tpcf_xi.hip"]
+SOURCES = ["tpcf.cpp", "tpcf_grid.hip", "tpcf_pairs.hip", "tpcf_contract.hip", "tpcf_xi.hip", "tpcf_cov.hip"]
 ARCH = os.environ.get("TPCF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -36,7 +36,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compiles every source and links libtpcf.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs

@@ -107,6 +107,8 @@ struct tpcf_handle_s {
 
     // 2PCF
     DevBuf d_xiq, d_xicoef, d_xirr, d_xiruns;
+    // covariance
+    DevBuf d_covx, d_covoff, d_covflag, d_covpart;
 
     // timing
     bool timing = false;
@@ -946,7 +948,8 @@ void tpcf_destroy(tpcf_handle h) {
                      &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_scanw, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag,
-                     &h->d_xiq, &h->d_xicoef, &h->d_xirr, &h->d_xiruns};
+                     &h->d_xiq, &h->d_xicoef, &h->d_xirr, &h->d_xiruns, &h->d_covx, &h->d_covoff,
+                     &h->d_covflag, &h->d_covpart};
     for (DevBuf* b : all) release(h, *b);
     h->magic = kDead;
     delete h;
@@ -1220,6 +1223,85 @@ tpcf_status tpcf_xi_multipoles(tpcf_handle h, int32_t nmu, const int64_t* d_coun
     t_begin(h, 4, t);
     HIPCHK(launch_xi_finalize(a, h->stream));
     t_end(h, t);
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_triangle_index(int32_t nbins, const double* h_edges, double eta, double r_min, int32_t n_rows,
+                                const int32_t* h_rows, int64_t capacity, int64_t* h_offsets, int64_t* h_count) {
+    if (nbins < 1 || nbins > kMaxBins || !h_edges || n_rows < 0 || (n_rows > 0 && !h_rows) || !h_count ||
+        capacity < 0 || (capacity > 0 && !h_offsets) || !(eta >= 0.0) || !std::isfinite(r_min))
+        return TPCF_ERR_ARG;
+    const double e0 = h_edges[0], dr = (h_edges[nbins] - e0) / nbins;
+    if (!(dr > 0.0)) return TPCF_ERR_RANGE;
+    for (int b = 0; b <= nbins; ++b)
+        if (std::fabs(h_edges[b] - (e0 + b * dr)) > 1e-9 * dr) return TPCF_ERR_RANGE;  // equal-width bins
+    for (int t = 0; t < n_rows; ++t)
+        if (h_rows[t] < 0) return TPCF_ERR_ARG;
+    int64_t n = 0;
+    for (int t = 0; t < n_rows; ++t)
+        for (int b1 = 0; b1 < nbins; ++b1)
+            for (int b2 = b1 + 1; b2 < nbins; ++b2) {
+                const double r1 = e0 + (b1 + 0.5) * dr, r2 = e0 + (b2 + 0.5) * dr;
+                if (r2 - r1 < (eta - 1e-9) * dr || r1 < r_min - 1e-9 * dr) continue;
+                if (n < capacity) h_offsets[n] = ((int64_t)h_rows[t] * nbins + b1) * nbins + b2;
+                ++n;
+            }
+    *h_count = n;
+    return n > capacity && capacity > 0 ? TPCF_ERR_RANGE : TPCF_OK;
+}
+
+tpcf_status tpcf_covariance(tpcf_handle h, int32_t n_mocks, int64_t stride, const double* d_src, int32_t n_d,
+                            const int64_t* h_offsets, double* d_mean, double* d_cov) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_src || !d_cov) return fail(h, TPCF_ERR_ARG, "NULL source or covariance");
+    if (n_mocks < 2) return fail(h, TPCF_ERR_ARG, "n_mocks must be >= 2");
+    if (n_d < 1 || stride < 1) return fail(h, TPCF_ERR_ARG, "n_d and stride must be >= 1");
+    if (!h_offsets && n_d > stride) return fail(h, TPCF_ERR_ARG, "n_d > stride without offsets");
+    if (h_offsets)
+        for (int i = 0; i < n_d; ++i)
+            if (h_offsets[i] < 0 || h_offsets[i] >= stride) return fail(h, TPCF_ERR_ARG, "offset outside a mock's row");
+    HIPCHK(hipSetDevice(h->device));
+    tpcf_status st;
+    if ((st = ensure(h, h->d_covx, sizeof(double) * (size_t)n_mocks * n_d)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_covpart, sizeof(double) * (size_t)cov_part_doubles(n_mocks, n_d))) != TPCF_OK)
+        return st;
+    const int64_t* doff = nullptr;
+    if (h_offsets) {
+        if ((st = upload(h, h->d_covoff, h_offsets, sizeof(int64_t) * n_d)) != TPCF_OK) return st;
+        doff = P<int64_t>(h->d_covoff);
+    }
+    HIPCHK(launch_cov(d_src, stride, doff, n_mocks, n_d, P<double>(h->d_covx), P<double>(h->d_covpart), d_mean, d_cov,
+                      h->stream));
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_precision_matrix(tpcf_handle h, int32_t n_d, const double* d_cov, int32_t n_mocks, double* d_prec) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_cov || !d_prec) return fail(h, TPCF_ERR_ARG, "NULL covariance or output");
+    if (n_d < 1 || n_d > 4096) return fail(h, TPCF_ERR_RANGE, "n_d must be in 1 .. 4096");
+    if (n_mocks < n_d + 3) return fail(h, TPCF_ERR_RANGE, "the Hartlap factor needs n_mocks >= n_d + 3");
+    HIPCHK(hipSetDevice(h->device));
+    tpcf_status st;
+    if ((st = ensure(h, h->d_covflag, sizeof(int))) != TPCF_OK) return st;
+    HIPCHK(launch_fill_i32(P<int>(h->d_covflag), 1, 0, h->stream));
+    if (d_prec != d_cov)
+        HIPCHK(hipMemcpyAsync(d_prec, d_cov, sizeof(double) * (size_t)n_d * n_d, hipMemcpyDeviceToDevice, h->stream));
+    const double hartlap = (n_mocks - n_d - 2.0) / (n_mocks - 1.0);
+    if ((st = ensure(h, h->d_covpart, sizeof(double) * (size_t)n_d * n_d)) != TPCF_OK) return st;
+    HIPCHK(launch_cov_invert(d_prec, P<double>(h->d_covpart), n_d, hartlap, P<int>(h->d_covflag), h->stream));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->d_covflag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (bad) return fail(h, TPCF_ERR_RANGE, "the covariance is not positive definite");
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_percival_m1(int32_t n_mocks, int32_t n_d, int32_t n_params, double* h_m1) {
+    if (!h_m1 || n_params < 0 || n_d < 1 || n_mocks < n_d + 5) return TPCF_ERR_ARG;
+    const double nm = n_mocks, nd = n_d, np = n_params;
+    const double den = (nm - nd - 1.0) * (nm - nd - 4.0);
+    const double A = 2.0 / den, B = (nm - nd - 2.0) / den;
+    *h_m1 = (1.0 + B * (nd - np)) / (1.0 + A + B * (np + 1.0));
     return TPCF_OK;
 }
 

@@ -175,6 +175,17 @@ struct XiFinalArgs {
 };
 hipError_t launch_xi_finalize(const XiFinalArgs& a, hipStream_t s);
 
+// Covariance over mock catalogues (tpcf_cov.hip)
+// X (nm x nd workspace) <- gathered data vectors, centred; C (nd x nd) <- X^T X / (nm - 1),
+// through cov_slices(nm, nd) partial products of nd x nd (workspace `part`).
+int cov_slices(int nm, int nd);
+int64_t cov_part_doubles(int nm, int nd);  // size of `part`: the slices' products and the mean's sums
+hipError_t launch_cov(const double* src, int64_t stride, const int64_t* off, int nm, int nd, double* X,
+                      double* part, double* mean, double* C, hipStream_t s);
+// A (n x n, symmetric positive definite) <- scale * A^-1 in place, W (n x n) as workspace;
+// *bad |= 1 on a non-positive pivot.
+hipError_t launch_cov_invert(double* A, double* W, int n, double scale, int* bad, hipStream_t s);
+
 // Contraction (tpcf_contract.hip)
 struct ContractArgs {
     const void* A;           // [nb][nvalues][ldA]

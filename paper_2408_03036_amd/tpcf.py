@@ -35,7 +35,8 @@ F_ISOTROPIC = 4
 EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
-           "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles"]
+           "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles", "tpcf_triangle_index",
+           "tpcf_covariance", "tpcf_precision_matrix", "tpcf_percival_m1"]
 
 
 class TpcfError(RuntimeError):
@@ -96,6 +97,14 @@ def load():
     lib.tpcf_xi_count.restype = st
     lib.tpcf_xi_multipoles.argtypes = [vp, i32, vp, i64, i32, vp, vp]
     lib.tpcf_xi_multipoles.restype = st
+    lib.tpcf_triangle_index.argtypes = [i32, vp, dbl, dbl, i32, vp, i64, vp, ctypes.POINTER(i64)]
+    lib.tpcf_triangle_index.restype = st
+    lib.tpcf_covariance.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
+    lib.tpcf_covariance.restype = st
+    lib.tpcf_precision_matrix.argtypes = [vp, i32, vp, i32, vp]
+    lib.tpcf_precision_matrix.restype = st
+    lib.tpcf_percival_m1.argtypes = [i32, i32, i32, ctypes.POINTER(dbl)]
+    lib.tpcf_percival_m1.restype = st
     _lib = lib
     return lib
 
@@ -237,6 +246,32 @@ class Handle:
                                               el.shape[0], ctypes.c_void_p(el.ctypes.data), _ptr(out)))
         return out
 
+    # -- covariance over mock catalogues (Sec. 4.3) -----------------------
+    def covariance(self, src, n_d=None, offsets=None):
+        """Mean and covariance of the rows of src (n_mocks x stride, float64 on the
+        GPU), over entries `offsets` (host int64) or the first n_d."""
+        import torch
+        _check_dev(src, torch.float64, "src")
+        nm, stride = src.shape
+        off = None if offsets is None else np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        nd = int(off.shape[0]) if off is not None else int(stride if n_d is None else n_d)
+        mean = torch.empty(nd, dtype=torch.float64, device=src.device)
+        cov = torch.empty((nd, nd), dtype=torch.float64, device=src.device)
+        self._chk(self.lib.tpcf_covariance(self.h, nm, stride, _ptr(src), nd,
+                                           None if off is None else ctypes.c_void_p(off.ctypes.data),
+                                           _ptr(mean), _ptr(cov)))
+        self._keep_off = off
+        return mean, cov
+
+    def precision(self, cov, n_mocks, out=None):
+        """Hartlap-corrected inverse of cov (eq. (Hartlap))."""
+        import torch
+        _check_dev(cov, torch.float64, "cov")
+        if out is None:
+            out = torch.empty_like(cov)
+        self._chk(self.lib.tpcf_precision_matrix(self.h, cov.shape[0], _ptr(cov), int(n_mocks), _ptr(out)))
+        return out
+
     def sync(self):
         self._chk(self.lib.tpcf_sync(self.h))
 
@@ -275,3 +310,34 @@ def estimate(pos, box, edges, lmax, mults, w=None, n_data=None, precision=PREC_M
     h.sync()
     h.close()
     return out
+
+
+def triangle_index(edges, eta, r_min, rows):
+    """Offsets of the 3PCF data vector in an n_mult x nbins x nbins block: for
+    each multipole row, configurations r1 < r2 with r2 - r1 >= eta dr and
+    r1 >= r_min (Sec. 4.3)."""
+    lib = load()
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1))
+    nb = edges.shape[0] - 1
+    cnt = ctypes.c_int64(0)
+    rc = lib.tpcf_triangle_index(nb, ctypes.c_void_p(edges.ctypes.data), float(eta), float(r_min), rows.shape[0],
+                                 ctypes.c_void_p(rows.ctypes.data), 0, None, ctypes.byref(cnt))
+    if rc != TPCF_OK:
+        raise TpcfError(rc, "tpcf_triangle_index rejected its arguments")
+    out = np.zeros(max(cnt.value, 1), dtype=np.int64)
+    rc = lib.tpcf_triangle_index(nb, ctypes.c_void_p(edges.ctypes.data), float(eta), float(r_min), rows.shape[0],
+                                 ctypes.c_void_p(rows.ctypes.data), out.shape[0], ctypes.c_void_p(out.ctypes.data),
+                                 ctypes.byref(cnt))
+    if rc != TPCF_OK:
+        raise TpcfError(rc, "tpcf_triangle_index failed")
+    return out[:cnt.value]
+
+
+def percival_m1(n_mocks, n_d, n_params):
+    """Percival factor m1 of eqs. (Perc1), (Perc)."""
+    v = ctypes.c_double(0.0)
+    rc = load().tpcf_percival_m1(int(n_mocks), int(n_d), int(n_params), ctypes.byref(v))
+    if rc != TPCF_OK:
+        raise TpcfError(rc, "tpcf_percival_m1 rejected its arguments")
+    return v.value

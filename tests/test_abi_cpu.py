@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "tpcf.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(tpcf_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(tpcf_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -98,3 +98,24 @@ def test_valid_config_without_gpu_reports_device(lib):
         pytest.skip("a GPU is present")
     rc, h = _create(lib)
     assert rc == T.TPCF_ERR_DEVICE
+
+
+def test_host_helpers_match_oracle(lib):
+    """tpcf_triangle_index and tpcf_percival_m1 need no device: compare with the
+    covariance oracle."""
+    from oracle import cov_oracle as V
+    edges = np.linspace(30.0, 150.0, 13)
+    for eta, rmin in [(1, 0.0), (3, 0.0), (1, 40.0), (2, 55.0)]:
+        sel = V.select_triangles(edges, eta, rmin)
+        off = T.triangle_index(edges, eta, rmin, [0, 4])
+        nb = 12
+        ref = [(t * nb + b1) * nb + b2 for t in (0, 4) for (b1, b2) in sel]
+        assert off.tolist() == ref, (eta, rmin)
+    for nm, nd, npar in [(3000, 336, 6), (298, 48, 4), (100, 90, 3)]:
+        assert abs(T.percival_m1(nm, nd, npar) - V.percival_m1(nm, nd, npar)) < 1e-14
+    with pytest.raises(T.TpcfError):
+        T.triangle_index([0.0, 1.0, 3.0], 1, 0.0, [0])  # unequal bins
+    with pytest.raises(T.TpcfError):
+        T.percival_m1(10, 8, 2)  # too few mocks
+    assert lib.tpcf_covariance(None, 10, 10, None, 5, None, None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_precision_matrix(None, 5, None, 10, None) == T.TPCF_ERR_ARG
