@@ -195,3 +195,33 @@ def xi_multipoles(counts, n_data, box, edges, ells) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_xi_multipoles rejected its arguments")
     return out
+
+
+# ------------------------------------------------------------------ edge correction (isotropic)
+
+
+def edge_correct_isotropic(N, R):
+    """Edge-corrected isotropic multipoles zeta_l(b1, b2) from the Legendre
+    multipoles N_l of the data-minus-randoms triplet counts and R_l of the
+    random triplet counts (both normalised the same way), by the published
+    Slepian-Eisenstein (2015) relation N(cos t) = zeta(cos t) R(cos t), which
+    with P_a P_b = sum_l (2l+1) (a b l; 0 0 0)^2 P_l reads
+        N_l = sum_{l'} M_{l l'} zeta_{l'},  M_{l l'} = sum_{l''} (2l+1) (l l' l''; 0 0 0)^2 R_{l''},
+    solved for each (b1, b2). N, R: [n_ell][nb][nb]; R is truncated at n_ell - 1."""
+    N = np.asarray(N, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    nl, nb1, nb2 = N.shape
+    out = np.zeros_like(N)
+    w3 = np.zeros((nl, nl, nl))
+    for l in range(nl):
+        for lp in range(nl):
+            for lpp in range(nl):
+                w3[l, lp, lpp] = (2 * l + 1) * wigner3j(l, lp, lpp, 0, 0, 0) ** 2
+    for b1 in range(nb1):
+        for b2 in range(nb2):
+            M = np.zeros((nl, nl))
+            for l in range(nl):
+                for lp in range(nl):
+                    M[l, lp] = sum(w3[l, lp, lpp] * R[lpp, b1, b2] for lpp in range(nl))
+            out[:, b1, b2] = np.linalg.solve(M, N[:, b1, b2])
+    return out
