@@ -226,6 +226,76 @@ def bench_xi(args):
     print(json.dumps(line))
 
 
+def bench_ss(args):
+    """Szapudi-Szalay estimator with explicit randoms at 50x (the paper's ratio):
+    a data-minus-randoms run and a randoms run on the isotropic schedule, then
+    the edge correction, on 1e4 clustered points with 5e5 randoms in a 400
+    Mpc/h box (the paper's halo density), 12 bins over [30, 150], l <= 4."""
+    import torch
+    from paper_2408_03036_amd import catalogs as C
+    from paper_2408_03036_amd import tpcf as T
+
+    box, nd = 400.0, 10_000
+    nr = 50 * nd
+    edges = np.linspace(30.0, 150.0, 13)
+    lmax = 4
+    iso = [(l, l, 0) for l in range(lmax + 1)]
+    print("[bench] generating data and randoms on the GPU", file=sys.stderr, flush=True)
+    D = C.zeldovich_torch(nd, box, 5.0, 0.8, C.catalogue_seed(90), grid=128, device="cuda:0")
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(C.randoms_seed(90))
+    Rp = (torch.rand((nr, 3), generator=g, device="cuda:0", dtype=torch.float64) * box).contiguous()
+    pos = torch.cat([D, Rp], dim=0).contiguous()
+    w = torch.from_numpy(C.dr_weights(nd, nr)).cuda()
+    prec = {"bf16x3": T.PREC_MIXED_BF16X3, "bf16x6": T.PREC_MIXED_BF16X6, "fp32": T.PREC_FP32,
+            "fp64": T.PREC_FP64}[args.precision]
+    hN = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC)
+    hR = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC)
+    hN.set_timing(True)
+    hR.set_timing(True)
+
+    def step():
+        Nm = hN.run_catalogs([nd + nr], [nd], pos, w, iso)
+        Rm = hR.run_catalogs([nr], [nr], Rp, None, iso)
+        return hN.edge_correct_isotropic(Nm[0], Rm[0])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hN.stage_times()
+    hR.stage_times()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        z = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    pairs = hN.pair_count() + hR.pair_count()
+    msN, nlN = hN.stage_times()
+    msR, nlR = hR.stage_times()
+    hN.close()
+    hR.close()
+    t_alm = (msN[2] + msR[2]) / max(nlN[2] + nlR[2], 1) / 1e3
+    launches = (nlN[2] + nlR[2]) / args.steps
+    achieved = pairs * flop_per_pair(lmax) / launches / t_alm
+    line = {
+        "metric": "pairs/s into a_lm(r), Szapudi-Szalay estimator with 50x explicit randoms, 1 GPU",
+        "value": pairs / dt, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec != T.PREC_FP64 else "f64", "data": "synthetic",
+        "config": {"workload": f"{nd} Zel'dovich+RSD points + {nr} randoms (50x), {box:.0f} Mpc/h box, 12 bins "
+                               f"[30,150] Mpc/h, isotropic l <= {lmax}, edge-corrected",
+                   "precision": args.precision, "pairs_per_step": int(pairs), "parallelism": "single GPU"},
+        "stages_ms": {k: (msN[i] + msR[i]) / args.steps for i, k in
+                      enumerate(["grid_ms", "pair_bin_ms", "pair_alm_ms", "contract_ms", "finalize_ms"])},
+        "roofline": {"kernel": f"k_pair_alm<float,{lmax}> (harmonic pass)", "bound": "alu",
+                     "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU, "traffic": None, "flop_per_pair": flop_per_pair(lmax),
+                     "avg_launch_ms": t_alm * 1e3, "launches_per_step": launches},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+
+
 def bench_cov(args):
     """Covariance step of Sec. 4.3 at the paper's size: 3000 mock data vectors of
     336 entries (the joint 2PCF + 3PCF vector of its covariance figure), taken
@@ -310,9 +380,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--refine", type=int, default=0)
-    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov"],
+    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov", "ss"],
                     help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF; "
-                         "cov: covariance and precision over mock data vectors")
+                         "cov: covariance and precision over mock data vectors; "
+                         "ss: Szapudi-Szalay estimator with 50x explicit randoms, edge-corrected")
     ap.add_argument("--isotropic", action="store_true",
                     help="3pcf: the isotropic schedule, multipoles (l, l, 0) only")
     args = ap.parse_args()
@@ -326,6 +397,9 @@ def main():
         return
     if args.workload == "cov":
         bench_cov(args)
+        return
+    if args.workload == "ss":
+        bench_ss(args)
         return
 
     import torch

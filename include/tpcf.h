@@ -205,6 +205,38 @@ tpcf_status tpcf_xi_multipoles(tpcf_handle h, int32_t nmu, const int64_t* d_coun
                                int32_t n_ell, const int32_t* h_ells, double* d_out);
 
 /*
+ * Autotuner of the neighbour grid. Times, on the sample catalogue (d_pos,
+ * d_w, n, n_data as for tpcf_build_grid), the pair pass (steps 1-2, nmu = 0)
+ * or the 2PCF pair counts (nmu > 0, unit weights) for every admissible grid
+ * refinement 1 .. 4 (cells of r_max / k), and keeps the fastest on the handle
+ * for later grids (it replaces the config's grid_refine). Results do not
+ * depend on the refinement: bin decisions are exact at every one.
+ *  h_refine: the refinement chosen.  h_ms: NULL, or 4 entries: the time of
+ *  each refinement in ms (-1 where it is not admissible for the box).
+ * The sample's grid is not kept: call tpcf_build_grid afterwards.
+ */
+tpcf_status tpcf_autotune(tpcf_handle h, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
+                          int32_t nmu, int32_t* h_refine, double* h_ms);
+
+/*
+ * Szapudi-Szalay estimator with explicit randoms (eq. (ssest)), isotropic
+ * multipoles: edge correction by the random triplet counts. With N_l the
+ * multipoles (l, l, 0) of a data-minus-randoms run (weights 1 and -N_D/N_R,
+ * n_data = N_D) and R_l those of a run on the randoms alone (n_data = N_R),
+ * both on the handle's bins, the relation N(cos t) = zeta(cos t) R(cos t)
+ * between the triplet counts as functions of the opening angle gives
+ *   N_l = sum_{l'} M_{l l'} zeta_{l'},  M_{l l'} = sum_{l''} (2l+1) (l l' l''; 0 0 0)^2 R_{l''}
+ * (the relation of Slepian & Eisenstein 2015; R truncated at n_ell - 1),
+ * solved for zeta at every (b1, b2) in FP64.
+ *  d_N, d_R, d_out: device, n_ell x nbins x nbins float64 ([l][b1][b2], l = 0 .. n_ell-1,
+ *                   as tpcf_multipoles writes the triples (l, l, 0) in order).
+ *  n_ell in 1 .. 25. A singular coupling matrix gives TPCF_ERR_RANGE.
+ *  Synchronises the stream.
+ */
+tpcf_status tpcf_edge_correct_isotropic(tpcf_handle h, int32_t n_ell, const double* d_N, const double* d_R,
+                                        double* d_out);
+
+/*
  * Covariance step of Sec. 4.3, for measurements of a suite of mock catalogues.
  *
  * tpcf_triangle_index: host helper building a 3PCF data vector. For each

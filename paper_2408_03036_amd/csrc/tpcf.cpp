@@ -109,6 +109,8 @@ struct tpcf_handle_s {
     DevBuf d_xiq, d_xicoef, d_xirr, d_xiruns;
     // covariance
     DevBuf d_covx, d_covoff, d_covflag, d_covpart;
+    // edge correction
+    DevBuf d_edgeT;
 
     // timing
     bool timing = false;
@@ -949,7 +951,7 @@ void tpcf_destroy(tpcf_handle h) {
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag,
                      &h->d_xiq, &h->d_xicoef, &h->d_xirr, &h->d_xiruns, &h->d_covx, &h->d_covoff,
-                     &h->d_covflag, &h->d_covpart};
+                     &h->d_covflag, &h->d_covpart, &h->d_edgeT};
     for (DevBuf* b : all) release(h, *b);
     h->magic = kDead;
     delete h;
@@ -1302,6 +1304,123 @@ tpcf_status tpcf_percival_m1(int32_t n_mocks, int32_t n_d, int32_t n_params, dou
     const double den = (nm - nd - 1.0) * (nm - nd - 4.0);
     const double A = 2.0 / den, B = (nm - nd - 2.0) / den;
     *h_m1 = (1.0 + B * (nd - np)) / (1.0 + A + B * (np + 1.0));
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_autotune(tpcf_handle h, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
+                          int32_t nmu, int32_t* h_refine, double* h_ms) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_pos || !h_refine) return fail(h, TPCF_ERR_ARG, "d_pos and h_refine are required");
+    if (n < 1 || n > (1LL << 27)) return fail(h, TPCF_ERR_ARG, "n must be in 1 .. 2^27");
+    if (n_data < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
+    if (nmu < 0) return fail(h, TPCF_ERR_ARG, "nmu must be >= 0");
+    if (nmu > 0 && d_w) return fail(h, TPCF_ERR_ARG, "the 2PCF pair counts take unit weights (d_w = NULL)");
+    HIPCHK(hipSetDevice(h->device));
+    tpcf_status st;
+    int64_t* d_counts = nullptr;
+    DevBuf counts;
+    if (nmu > 0) {
+        if ((st = ensure(h, counts, sizeof(int64_t) * (size_t)h->nb * nmu)) != TPCF_OK) return st;
+        d_counts = P<int64_t>(counts);
+    }
+    const bool timing = h->timing;
+    h->timing = false;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = 0, last_k = -1;
+    double best_ms = 0.0;
+    st = TPCF_OK;
+    for (int k = 1; k <= 4 && st == TPCF_OK; ++k) {
+        if (h_ms) h_ms[k - 1] = -1.0;
+        h->refine = k;
+        h->stage = 0;
+        if ((st = build_grid_group(h, d_pos, d_w, {n}, {n_data})) != TPCF_OK) break;
+        h->stage = 1;
+        if (h->g.k == last_k || (h->g.k != k && !h->g.single)) continue;  // not admissible: fell back
+        last_k = h->g.k;
+        if ((st = check_nonfinite(h)) != TPCF_OK) break;
+        if (nmu == 0 && (st = plan_chunks(h)) != TPCF_OK) break;
+        // one untimed pass, then the timed one
+        double ms = 0.0;
+        for (int rep = 0; rep < 2 && st == TPCF_OK; ++rep) {
+            if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(h, TPCF_ERR_DEVICE, "hipEventRecord"); break; }
+            st = nmu > 0 ? tpcf_xi_count(h, nmu, d_counts) : pair_pass(h, false);
+            if (st != TPCF_OK) break;
+            if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(h, TPCF_ERR_DEVICE, "hipEvent");
+                break;
+            }
+            float f = 0.f;
+            hipEventElapsedTime(&f, e0, e1);
+            ms = f;
+        }
+        if (st != TPCF_OK) break;
+        if (h_ms) h_ms[k - 1] = ms;
+        if (best == 0 || ms < best_ms) {
+            best = h->g.single ? k : h->g.k;
+            best_ms = ms;
+        }
+        if (h->g.single) break;  // every refinement gives the one-cell grid
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    release(h, counts);
+    h->timing = timing;
+    h->stage = 0;  // the grid of the sample is not kept
+    h->pairs_valid = false;
+    if (st != TPCF_OK) {
+        h->refine = h->cfg.grid_refine;
+        return st;
+    }
+    h->refine = best;
+    *h_refine = best;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_edge_correct_isotropic(tpcf_handle h, int32_t n_ell, const double* d_N, const double* d_R,
+                                        double* d_out) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_N || !d_R || !d_out) return fail(h, TPCF_ERR_ARG, "NULL multipoles or output");
+    if (n_ell < 1 || n_ell > 25) return fail(h, TPCF_ERR_RANGE, "n_ell must be in 1 .. 25");
+    HIPCHK(hipSetDevice(h->device));
+    // T[l][l'][l''] = (2l+1)/2 int_{-1}^{1} P_l P_l' P_l'' dx, by Gauss-Legendre quadrature
+    // (exact: the integrand has degree <= 3 (n_ell - 1) <= 72 < 2 * 40)
+    const int nl = n_ell;
+    std::vector<double> gx, gw;
+    gauss_legendre(40, gx, gw);
+    std::vector<double> Pq(gx.size() * nl);
+    for (size_t q = 0; q < gx.size(); ++q) {
+        double p0 = 1.0, p1 = gx[q];
+        for (int l = 0; l < nl; ++l) {
+            double v;
+            if (l == 0) v = 1.0;
+            else if (l == 1) v = gx[q];
+            else {
+                v = ((2.0 * l - 1.0) * gx[q] * p1 - (l - 1.0) * p0) / l;
+                p0 = p1;
+                p1 = v;
+            }
+            Pq[q * nl + l] = v;
+        }
+    }
+    std::vector<double> T((size_t)nl * nl * nl, 0.0);
+    for (int l = 0; l < nl; ++l)
+        for (int lp = 0; lp < nl; ++lp)
+            for (int lpp = 0; lpp < nl; ++lpp) {
+                double s = 0.0;
+                for (size_t q = 0; q < gx.size(); ++q) s += gw[q] * Pq[q * nl + l] * Pq[q * nl + lp] * Pq[q * nl + lpp];
+                T[((size_t)l * nl + lp) * nl + lpp] = 0.5 * (2.0 * l + 1.0) * s;
+            }
+    tpcf_status st;
+    if ((st = upload(h, h->d_edgeT, T.data(), sizeof(double) * T.size())) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_covflag, sizeof(int))) != TPCF_OK) return st;
+    HIPCHK(launch_fill_i32(P<int>(h->d_covflag), 1, 0, h->stream));
+    HIPCHK(launch_edge_iso(d_N, d_R, P<double>(h->d_edgeT), nl, h->nb * h->nb, d_out, P<int>(h->d_covflag), h->stream));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->d_covflag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (bad) return fail(h, TPCF_ERR_RANGE, "singular coupling matrix (random multipoles)");
     return TPCF_OK;
 }
 

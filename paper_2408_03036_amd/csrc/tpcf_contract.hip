@@ -18,9 +18,13 @@
 // the partials are reduced per catalogue in a fixed order in FP64, so the
 // result does not depend on scheduling.
 //
-// The same file holds the degenerate-triangle moments, the fixed-order partial
-// reduction, and the final conversion to the tripolar multipoles
-// (eq. (slep2sugy)).
+// The same file holds the isotropic schedule (the l1 = l2 blocks only), the
+// degenerate-triangle moments, the fixed-order partial reduction, the final
+// conversion to the tripolar multipoles (eq. (slep2sugy)) and the edge
+// correction of isotropic multipoles by explicit random triplet counts.
+#include <algorithm>
+#include <type_traits>
+
 #include "tpcf_internal.h"
 
 namespace tpcf {
@@ -754,6 +758,62 @@ __global__ void k_finalize(FinalArgs a) {
     a.out[(int64_t)c * per + idx] = sum / rrr;
 }
 
+// Edge correction of the isotropic multipoles for the Szapudi-Szalay estimator
+// with explicit randoms (eq. (ssest)): the triplet counts of the data-minus-
+// randoms field and of the randoms are related as functions of the opening
+// angle by N = zeta R, which for Legendre coefficients reads
+//   N_l = sum_{l'} M_{l l'} zeta_{l'},  M_{l l'} = sum_{l''} T[l][l'][l''] R_{l''},
+// with T[l][l'][l''] = (2l+1)/2 int P_l P_l' P_l'' (the relation of Slepian &
+// Eisenstein 2015). One thread per (b1, b2) forms M in LDS and solves by
+// Gaussian elimination with partial pivoting in FP64; a singular M sets *bad.
+__global__ void k_edge_iso(const double* __restrict__ N, const double* __restrict__ R, const double* __restrict__ T,
+                           int nl, int nbb, double* __restrict__ out, int* __restrict__ bad) {
+    extern __shared__ double esh[];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nbb) return;
+    double* M = esh + (size_t)threadIdx.x * (nl * nl + nl);
+    double* x = M + nl * nl;
+    for (int l = 0; l < nl; ++l) {
+        x[l] = N[(int64_t)l * nbb + q];
+        for (int lp = 0; lp < nl; ++lp) {
+            double v = 0.0;
+            for (int lpp = 0; lpp < nl; ++lpp) v += T[(l * nl + lp) * nl + lpp] * R[(int64_t)lpp * nbb + q];
+            M[l * nl + lp] = v;
+        }
+    }
+    for (int c = 0; c < nl; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < nl; ++r)
+            if (fabs(M[r * nl + c]) > fabs(M[piv * nl + c])) piv = r;
+        if (!(fabs(M[piv * nl + c]) > 0.0)) {
+            atomicOr(bad, 1);
+            return;
+        }
+        if (piv != c) {
+            for (int k = 0; k < nl; ++k) {
+                const double t = M[c * nl + k];
+                M[c * nl + k] = M[piv * nl + k];
+                M[piv * nl + k] = t;
+            }
+            const double t = x[c];
+            x[c] = x[piv];
+            x[piv] = t;
+        }
+        const double ip = 1.0 / M[c * nl + c];
+        for (int r = c + 1; r < nl; ++r) {
+            const double f = M[r * nl + c] * ip;
+            for (int k = c; k < nl; ++k) M[r * nl + k] -= f * M[c * nl + k];
+            x[r] -= f * x[c];
+        }
+    }
+    for (int c = nl - 1; c >= 0; --c) {
+        double v = x[c];
+        for (int k = c + 1; k < nl; ++k) v -= M[c * nl + k] * x[k];
+        x[c] = v / M[c * nl + c];
+    }
+    for (int l = 0; l < nl; ++l) out[(int64_t)l * nbb + q] = x[l];
+}
+
 __global__ void k_export_nnn(NnnArgs a) {
     const int nb = a.nb, s1 = a.lmax + 1, nL = 2 * a.lmax + 1;
     const int64_t n = (int64_t)s1 * s1 * s1 * nb * nb;
@@ -937,6 +997,23 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     const int64_t per = (int64_t)a.n_mult * a.nb * a.nb;
     if (per <= 0 || a.ncat <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((per + 255) / 256), a.ncat), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_iso(const double* N, const double* R, const double* T, int nl, int nbb, double* out, int* bad,
+                           hipStream_t s) {
+    if (nbb <= 0 || nl <= 0) return hipSuccess;
+    // one system (nl^2 + nl doubles) per thread in LDS: up to 32 threads, within 160 KiB
+    const size_t per = (size_t)(nl * nl + nl) * sizeof(double);
+    const int kThreads = (int)std::max<size_t>(1, std::min<size_t>(32, (size_t)160 * 1024 / per));
+    const size_t lds = (size_t)kThreads * per;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_edge_iso, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_edge_iso, dim3((nbb + kThreads - 1) / kThreads), dim3(kThreads), lds, s, N, R, T, nl, nbb,
+                       out, bad);
     return hipGetLastError();
 }
 

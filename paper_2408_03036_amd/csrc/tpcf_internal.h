@@ -247,6 +247,11 @@ struct FinalArgs {
 };
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 
+// Edge correction of isotropic multipoles: out[l][q] solves sum_l' M_{l l'} out[l'][q] = N[l][q],
+// M_{l l'} = sum_l'' T[(l nl + l') nl + l''] R[l''][q], q < nbb (= nb^2); *bad |= 1 if singular.
+hipError_t launch_edge_iso(const double* N, const double* R, const double* T, int nl, int nbb, double* out, int* bad,
+                           hipStream_t s);
+
 struct NnnArgs {
     const double* G;         // [gsize] one catalogue
     const int64_t* goff;

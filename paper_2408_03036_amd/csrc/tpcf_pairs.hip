@@ -78,9 +78,9 @@ __device__ __noinline__ int exact_pair(const double4* pd, int64_t p, int64_t cst
 
 constexpr int kNW = 4;                     // wavefronts per workgroup
 constexpr int kGM = kItemPrims / kNW;      // primaries per wavefront
-constexpr int kTile = 512;                 // candidates per LDS tile
+constexpr int kTile = 256;                 // candidates per LDS tile
 constexpr int kUT = kTile / 64;            // tile candidates per lane
-constexpr int kStage = kTile / (64 * kNW); // candidates each thread stages per tile
+constexpr int kStage = (kTile + 64 * kNW - 1) / (64 * kNW); // candidates each thread stages per tile
 constexpr uint32_t kNoBase = 0xffffffffu;
 static_assert(kGM * kNW == kItemPrims, "item size");
 
@@ -150,6 +150,7 @@ struct ItemCtx {
     int64_t cs, cstart;     // first primary of this wavefront's group, catalogue start
     uint32_t cst, mask;
     int cshift, cx, cy, cz, wave, lane, ng;
+    int slot;               // allocation region: (work item, wavefront) spread over all kSlots
 };
 
 // One sweep over the item's candidates. SWEEP 0 counts the hits of every
@@ -167,13 +168,17 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
     const float lo2 = T.e2f[0] - T.guard[0];
     const float hi2 = T.e2f[a.nb] + T.guard[a.nb];
     const unsigned nbu = (unsigned)a.nb;
+    // thread x stages tile slots x, x + 64 kNW, ... below kTile
     Staged st[kStage];
 #pragma unroll
     for (int s = 0; s < kStage; ++s) {
         st[s].r = 0;
+        st[s].ok = false;
         const int i = s * 64 * kNW + threadIdx.x;
-        stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, i, a.pf, a.pw);
-        stage_store<SINGLE>(st[s], c.tiles + i, c.tent + i, c.cst, c.cshift, a.g.hf);
+        if (i < kTile) {
+            stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, i, a.pf, a.pw);
+            stage_store<SINGLE>(st[s], c.tiles + i, c.tent + i, c.cst, c.cshift, a.g.hf);
+        }
     }
     __syncthreads();
     int buf = 0;
@@ -184,8 +189,9 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
         if (more) {
 #pragma unroll
             for (int s = 0; s < kStage; ++s)
-                stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, t + kTile + s * 64 * kNW + (int)threadIdx.x,
-                                        a.pf, a.pw);
+                if (s * 64 * kNW + (int)threadIdx.x < kTile)
+                    stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, t + kTile + s * 64 * kNW + (int)threadIdx.x,
+                                            a.pf, a.pw);
         }
         const int nt = min(kTile, c.total - t);
 #pragma unroll 2
@@ -246,9 +252,10 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
         if (more) {
 #pragma unroll
             for (int s = 0; s < kStage; ++s)
-                stage_store<SINGLE>(st[s], c.tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x,
-                                    c.tent + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, c.cst, c.cshift,
-                                    a.g.hf);
+                if (s * 64 * kNW + (int)threadIdx.x < kTile)
+                    stage_store<SINGLE>(st[s], c.tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x,
+                                        c.tent + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, c.cst, c.cshift,
+                                        a.g.hf);
         }
         __syncthreads();
         buf ^= 1;
@@ -279,8 +286,7 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
         sum += tot[g];
     }
     if (c.ng == 0) return;
-    const int64_t pl0 = c.cs + c.wave - a.p_begin;
-    const int slot = (int)(pl0 % kSlots);
+    const int slot = c.slot;
     const unsigned long long region = a.capacity / kSlots;
     unsigned long long b0 = 0;
     if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
@@ -342,20 +348,24 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
 
     int gc;
     int64_t first, last;
+    int64_t item;
     if constexpr (FIX) {
-        const int64_t item = xcd_block(blockIdx.x, (int64_t)gridDim.x);
+        item = xcd_block(blockIdx.x, (int64_t)gridDim.x);
         if (item >= a.nfix_items) return;
         const int2 f = a.fix[item];
         gc = f.x;
         first = a.p_begin + f.y;
         last = first + 1;
     } else {
-        const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
+        item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
         if (item >= a.item_hi) return;
         gc = a.item_cell[item];
         first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
         last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
     }
+    // consecutive (item, wavefront) pairs take consecutive regions, so every
+    // region serves about the same number of primaries whatever the cell sizes
+    c.slot = (int)((item * kNW + c.wave) % kSlots);
     c.cs = max(first, a.p_begin);
     const int64_t ce = min(last, a.p_end);
     if (c.cs >= ce) return;
@@ -422,8 +432,7 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
         bool ok = true;
         if (c.ng > 0) {
             const unsigned long long sum = (unsigned long long)captot * (unsigned)c.ng;
-            const int64_t pl0 = c.cs + c.wave - a.p_begin;
-            const int slot = (int)(pl0 % kSlots);
+            const int slot = c.slot;
             const unsigned long long region = a.capacity / kSlots;
             unsigned long long b0 = 0;
             if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, sum);

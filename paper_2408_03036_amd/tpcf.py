@@ -36,7 +36,8 @@ EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
            "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles", "tpcf_triangle_index",
-           "tpcf_covariance", "tpcf_precision_matrix", "tpcf_percival_m1"]
+           "tpcf_covariance", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic",
+           "tpcf_autotune"]
 
 
 class TpcfError(RuntimeError):
@@ -105,6 +106,10 @@ def load():
     lib.tpcf_precision_matrix.restype = st
     lib.tpcf_percival_m1.argtypes = [i32, i32, i32, ctypes.POINTER(dbl)]
     lib.tpcf_percival_m1.restype = st
+    lib.tpcf_edge_correct_isotropic.argtypes = [vp, i32, vp, vp, vp]
+    lib.tpcf_edge_correct_isotropic.restype = st
+    lib.tpcf_autotune.argtypes = [vp, vp, vp, i64, i64, i32, ctypes.POINTER(i32), vp]
+    lib.tpcf_autotune.restype = st
     _lib = lib
     return lib
 
@@ -179,6 +184,19 @@ class Handle:
         self._chk(self.lib.tpcf_build_grid(self.h, _ptr(pos), _ptr(w), n,
                                            n if n_data is None else int(n_data)))
 
+    def autotune(self, pos, w=None, n_data=None, nmu=0):
+        """Times every admissible grid refinement on the sample catalogue and keeps
+        the fastest; returns (refinement, ms per refinement 1..4, -1 if not admissible)."""
+        import torch
+        _check_dev(pos, torch.float64, "pos")
+        _check_dev(w, torch.float64, "w")
+        n = pos.shape[0]
+        k = ctypes.c_int32(0)
+        ms = np.zeros(4)
+        self._chk(self.lib.tpcf_autotune(self.h, _ptr(pos), _ptr(w), n, n if n_data is None else int(n_data),
+                                         int(nmu), ctypes.byref(k), ctypes.c_void_p(ms.ctypes.data)))
+        return int(k.value), ms
+
     def alm_accumulate(self):
         self._chk(self.lib.tpcf_alm_accumulate(self.h))
 
@@ -244,6 +262,19 @@ class Handle:
         out = torch.empty((el.shape[0], self.nbins), dtype=torch.float64, device=f"cuda:{self.device}")
         self._chk(self.lib.tpcf_xi_multipoles(self.h, int(counts.shape[1]), _ptr(counts), int(n_data),
                                               el.shape[0], ctypes.c_void_p(el.ctypes.data), _ptr(out)))
+        return out
+
+    # -- Szapudi-Szalay estimator with explicit randoms -------------------
+    def edge_correct_isotropic(self, N, R):
+        """zeta_l(b1, b2) from the (l, l, 0) multipoles N of a data-minus-randoms
+        run and R of a randoms run ([n_ell][nb][nb] float64 on the GPU)."""
+        import torch
+        _check_dev(N, torch.float64, "N")
+        _check_dev(R, torch.float64, "R")
+        if N.shape != R.shape or N.shape[1:] != (self.nbins, self.nbins):
+            raise ValueError("N and R must both be [n_ell][nbins][nbins]")
+        out = torch.empty_like(N)
+        self._chk(self.lib.tpcf_edge_correct_isotropic(self.h, N.shape[0], _ptr(N), _ptr(R), _ptr(out)))
         return out
 
     # -- covariance over mock catalogues (Sec. 4.3) -----------------------

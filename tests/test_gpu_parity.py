@@ -355,3 +355,33 @@ def test_isotropic_rejects_anisotropic_triples(torch):
         h.multipoles([(2, 0, 2)])
     assert e.value.status == T.TPCF_ERR_ARG
     h.close()
+
+
+# ------------------------------------------------------------------ autotuner
+
+
+def test_autotune_keeps_results(torch, dense_case):
+    """The autotuner picks an admissible grid refinement by timing; the pair
+    count is unchanged and the FP64 multipoles agree to rounding."""
+    pos, mults, ref, res = dense_case
+    h = T.Handle(DENSE["box"], DENSE["edges"], DENSE["lmax"], precision=T.PREC_FP64)
+    P = gpu(torch, pos)
+    k, ms = h.autotune(P)
+    say(f"  autotune: refinement {k}, ms per refinement {np.round(ms, 2).tolist()}")
+    assert 1 <= k <= 4 and ms[k - 1] > 0 and ms[k - 1] == ms[ms > 0].min()
+    h.build_grid(P)
+    h.alm_accumulate()
+    h.contract()
+    out = h.multipoles(mults).cpu().numpy()
+    h.sync()
+    assert h.pair_count() == res.npairs
+    h.close()
+    assert rel_err(out, ref) < 1e-12
+    # the 2PCF counts tuned the same way
+    h = T.Handle(400.0, np.linspace(0.0, 60.0, 13), 0)
+    k2, ms2 = h.autotune(P, nmu=40)
+    assert 1 <= k2 <= 4 and ms2[k2 - 1] == ms2[ms2 > 0].min()
+    h.build_grid(P)
+    dd = h.xi_count(40).cpu().numpy()
+    h.close()
+    assert np.array_equal(dd, O.xi_counts(pos, 400.0, np.linspace(0.0, 60.0, 13), 40))
