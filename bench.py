@@ -249,8 +249,9 @@ def bench_ss(args):
     w = torch.from_numpy(C.dr_weights(nd, nr)).cuda()
     prec = {"bf16x3": T.PREC_MIXED_BF16X3, "bf16x6": T.PREC_MIXED_BF16X6, "fp32": T.PREC_FP32,
             "fp64": T.PREC_FP64}[args.precision]
-    hN = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC)
-    hR = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC)
+    # the neighbour lists of 1e5 randoms per primary need room: 200 GiB of the 288 GB
+    hN = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+    hR = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
     hN.set_timing(True)
     hR.set_timing(True)
 

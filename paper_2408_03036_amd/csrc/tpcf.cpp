@@ -44,6 +44,7 @@ struct Chunk {
     int64_t p_begin, p_end;  // sorted indices
     int sub_begin, sub_end;  // global subchunk range
     int sub_off;             // offset of the chunk's relative subchunk table in d_subs
+    int64_t item_lo = -1, item_hi = -1;  // exact work items of the chunk (one catalogue), or -1
 };
 
 }  // namespace
@@ -92,6 +93,7 @@ struct tpcf_handle_s {
     float inv_dr = 0.f;   // 1 / bin width (uniform bins)
     float delta = 0.f;    // FP32 guard band in units of the bin width
     int64_t chunk_cap = 0;
+    double hits_per_list = 0.0;  // predicted mean length of a (p, b) list
     unsigned long long list_cap = 0;
     DevBuf d_fix;
     int64_t nfix_total = 0;   // primaries rebinned with exact counts (all chunks since creation)
@@ -584,9 +586,12 @@ tpcf_status plan_chunks(tpcf_handle h) {
         hits_room += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
     }
     const double list_per = lelem * hits_room;
+    h->hits_per_list = hits / h->nb;
     int64_t budget = h->limit / 2;
     int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
     cap = std::min<int64_t>(cap, 1 << 20);
+    // list offsets are 32-bit: keep a chunk's predicted room within 3.5e9 entries
+    cap = std::min<int64_t>(cap, (int64_t)(3.5e9 / hits_room));
     cap = std::max<int64_t>(h->kc, cap / h->kc * h->kc);
     h->chunk_cap = cap;
     h->sub_start.clear();
@@ -612,6 +617,25 @@ tpcf_status plan_chunks(tpcf_handle h) {
     }
     int64_t maxch = 0;
     for (auto& ch : h->chunks) maxch = std::max(maxch, ch.p_end - ch.p_begin);
+    // One catalogue split over several chunks: launch only the work items
+    // holding each chunk's primaries (from host copies of the cell and item
+    // starts) rather than every item of the catalogue.
+    if (h->ncat == 1 && h->chunks.size() > 1) {
+        const int64_t M = h->g.ncell;
+        std::vector<int> cs(M + 1), is(M + 1);
+        HIPCHK(hipMemcpyAsync(cs.data(), h->d_start.p, sizeof(int) * (M + 1), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(is.data(), h->d_istart.p, sizeof(int) * (M + 1), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        auto item_of = [&](int64_t p) {
+            // the cell holding sorted point p, then its block of kItemPrims
+            const int64_t c = std::upper_bound(cs.begin(), cs.end(), (int)p) - cs.begin() - 1;
+            return (int64_t)is[c] + (p - cs[c]) / kItemPrims;
+        };
+        for (auto& ch : h->chunks) {
+            ch.item_lo = item_of(ch.p_begin);
+            ch.item_hi = item_of(ch.p_end - 1) + 1;
+        }
+    }
     h->ldA = (maxch + 63) / 64 * 64;
     h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, (double)maxch * hits_room));
     tpcf_status st;
@@ -684,6 +708,10 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
             while (c1 + 1 < h->ncat && h->pt_off[c1 + 1] < ch.p_end) ++c1;
             b.item_lo = h->item_cat[c0];
             b.item_hi = h->item_cat[c1 + 1];
+            if (ch.item_lo >= 0) {
+                b.item_lo = ch.item_lo;
+                b.item_hi = ch.item_hi;
+            }
         }
         Timer t;
         t_begin(h, 1, t);
@@ -724,6 +752,9 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     a.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
     a.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
     a.unit_w = h->unit_w ? 1 : 0;
+    // a wavefront per list once lists average 256 records or more (the
+    // predicted hits of a primary of the densest catalogue, over the bins)
+    a.wave_per_list = (!h->fp64 && h->lmax <= 6 && h->hits_per_list >= 256.0) ? 1 : 0;
     a.boff = P<uint32_t>(h->d_boff);
     a.cnt = P<uint32_t>(h->d_cnt);
     a.A = h->d_A.p;

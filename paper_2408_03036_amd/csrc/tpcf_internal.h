@@ -125,6 +125,7 @@ struct AlmArgs {
     const uint32_t* list;    // list entries (FP64 path)
     const float4* rec;       // hit records (dx, dy, dz, w_j) (FP32 paths)
     int unit_w;              // all weights are 1
+    int wave_per_list;       // long lists: one wavefront per (p, b) list (FP32, lmax <= 6)
     const uint32_t* boff;
     const uint32_t* cnt;
     void* A;                 // [nb][nvalues][ldA] float or double

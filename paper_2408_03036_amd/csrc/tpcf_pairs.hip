@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         n = a.cnt[pl * a.nb + b];
         off = a.boff[pl * a.nb + b];
     }
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && (LMAX >= 8 || G != 0)) {
         // FP32: the binning pass wrote each hit as (dx, dy, dz, w_j); records
         // two hits ahead are in flight while a hit is accumulated.
         const float4* rec = a.rec + off;
@@ -608,6 +608,27 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
             add_hit<T, LMAX, G, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
             r0 = r1;
             r1 = r2;
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        // Low lmax: too little arithmetic per hit to cover the memory latency
+        // with two records in flight, so a ring of D records (slot i holds
+        // records t + i; the record D ahead is loaded into the slot just read).
+        constexpr int D = LMAX <= 4 ? 8 : 4;
+        const float4* rec = a.rec + off;
+        float4 q[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) q[i] = (uint32_t)i < n ? rec[i] : make_float4(1.f, 0.f, 0.f, 0.f);
+        for (uint32_t t = 0; t < n; t += D) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const float4 r0 = q[i];
+                if (t + i + D < n) q[i] = rec[t + i + D];
+                if (t + i < n) {
+                    const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
+                    const float inv = __builtin_amdgcn_rsqf(d2);
+                    add_hit<T, LMAX, G, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
+                }
+            }
         }
     } else {
         // FP64: list entries two hits ahead and the point one hit ahead.
@@ -657,9 +678,80 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
     }
 }
 
+// Long lists (thousands of neighbours per (p, b), for example with many
+// randoms): one wavefront per list, its 64 lanes taking consecutive records
+// (each load is one contiguous 1 KiB block), every lane accumulating its own
+// partial sums, which a butterfly of lane exchanges adds in a fixed order at
+// the end. A lane per list would touch 64 cache lines per load there and
+// thrash L1. FP32 and lmax <= 6 (higher orders have the arithmetic to hide
+// the lane-per-list loads, and their partial sums would cost occupancy).
+constexpr int kWaveListWaves = 4;
+
+template <int LMAX, bool UNIT>
+__global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a) {
+    using AC = Acc<float, LMAX, 0>;
+    constexpr int NV = n_values(LMAX);
+    const int lane = lane_id();
+    const int64_t nprim = a.p_end - a.p_begin;
+    const int64_t wv = xcd_block(blockIdx.x, (int64_t)gridDim.x) * kWaveListWaves + (threadIdx.x >> 6);
+    if (wv >= nprim * a.nb) return;
+    const int64_t pl = wv / a.nb;
+    const int b = (int)(wv - pl * a.nb);
+    AC acc;
+#pragma unroll
+    for (int i = 0; i < AC::NA; ++i) acc.a[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < AC::NS; ++i) acc.s[i] = 0.f;
+    const uint32_t n = a.cnt[pl * a.nb + b];
+    const float4* rec = a.rec + a.boff[pl * a.nb + b];
+    float4 r0 = (uint32_t)lane < n ? rec[lane] : make_float4(1.f, 0.f, 0.f, 0.f);
+    for (uint32_t t = lane; t < n; t += 64) {
+        const float4 r1 = t + 64 < n ? rec[t + 64] : make_float4(1.f, 0.f, 0.f, 0.f);
+        const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
+        const float inv = __builtin_amdgcn_rsqf(d2);
+        add_hit<float, LMAX, 0, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
+        r0 = r1;
+    }
+    // every lane ends with the total of every value
+#pragma unroll
+    for (int i = 0; i < AC::NA; ++i)
+        for (int o = 32; o > 0; o >>= 1) acc.a[i] += __shfl_xor(acc.a[i], o, 64);
+    if constexpr (UNIT) {
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l];
+#pragma unroll
+        for (int i = LMAX + 1; i < AC::NS; ++i)
+            for (int o = 32; o > 0; o >>= 1) acc.s[i] += __shfl_xor(acc.s[i], o, 64);
+    } else {
+#pragma unroll
+        for (int i = 0; i < AC::NS; ++i)
+            for (int o = 32; o > 0; o >>= 1) acc.s[i] += __shfl_xor(acc.s[i], o, 64);
+    }
+    // lane i writes value i
+    float* A = reinterpret_cast<float*>(a.A);
+    const int64_t ld = a.ldA;
+#pragma unroll
+    for (int i = 0; i < AC::NA; ++i)
+        if (lane == i % 64) A[((int64_t)b * NV + i) * ld + pl] = acc.a[i];
+#pragma unroll
+    for (int i = 0; i < AC::NS; ++i)
+        if (lane == (AC::NA + i) % 64) A[((int64_t)b * NV + n_alm_values(LMAX) + i) * ld + pl] = acc.s[i];
+}
+
 template <typename T, int LMAX, int G>
 hipError_t launch_alm_one(const AlmArgs& a, hipStream_t s) {
     const int64_t nprim = a.p_end - a.p_begin;
+    if constexpr (sizeof(T) == 4 && G == 0 && LMAX <= 6) {
+        if (a.wave_per_list) {
+            const int64_t nw = (nprim * a.nb + kWaveListWaves - 1) / kWaveListWaves;
+            const int64_t nwg = (nw + 7) / 8 * 8;
+            if (a.unit_w)
+                hipLaunchKernelGGL((k_pair_alm_wave<LMAX, true>), dim3((unsigned)nwg), dim3(64 * kWaveListWaves), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_pair_alm_wave<LMAX, false>), dim3((unsigned)nwg), dim3(64 * kWaveListWaves), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     const int64_t nwaves = ((nprim + 255) / 256) * a.nb * 4;
     const int64_t nwg = (nwaves + 7) / 8 * 8;
     // unit weights: the FP32 single-launch kernel shares the m = 0 sums

@@ -385,3 +385,43 @@ def test_autotune_keeps_results(torch, dense_case):
     dd = h.xi_count(40).cpu().numpy()
     h.close()
     assert np.array_equal(dd, O.xi_counts(pos, 400.0, np.linspace(0.0, 60.0, 13), 40))
+
+
+# ------------------------------------------------------------------ long lists
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_long_lists_wave_kernel(torch, weighted):
+    """Hundreds of neighbours per (primary, bin) at lmax 4 (the wavefront-per-list
+    harmonic kernel): a_lm of a slice of primaries against the oracle (FP32
+    tolerance), and the multipoles against the FP64 path."""
+    box, edges, lmax = 100.0, np.linspace(2.0, 20.0, 5), 4
+    n = 40000
+    pos = C.zeldovich(n, box, 2.0, 0.8, C.catalogue_seed(95), grid=64)
+    w = None
+    if weighted:
+        w = np.random.default_rng(95).uniform(0.5, 1.5, n)
+    mults = O.all_multipoles(lmax, 4)
+    outs = {}
+    for prec in (T.PREC_FP32, T.PREC_FP64):
+        h = T.Handle(box, edges, lmax, precision=prec)
+        h.build_grid(gpu(torch, pos), gpu(torch, w))
+        h.alm_accumulate()
+        alm = h.get_alm(12345, 32).cpu().numpy()
+        h.contract()
+        outs[prec] = h.multipoles(mults).cpu().numpy()
+        h.sync()
+        h.close()
+        if prec == T.PREC_FP32:
+            ref = O.estimate(pos, box, edges, lmax, w=w, prim_first=12345, prim_count=32, want_alm=True,
+                             want_nnn=False).alm
+            mask = np.tril(np.ones((lmax + 1, lmax + 1), dtype=bool))
+            err = float(np.abs(alm[..., mask] - ref[..., mask]).max() / np.abs(ref[..., mask]).max())
+            say(f"  long lists a_lm slice rel err {err:.2e} (weighted={weighted})")
+            assert err < 1e-5
+            # a_00 = count / sqrt(4 pi) for unit weights: lists average several hundred
+            if not weighted:
+                assert np.mean(ref[:, :, 0, 0].real) * math.sqrt(4 * math.pi) > 256
+    err = rel_err(outs[T.PREC_FP32], outs[T.PREC_FP64])
+    say(f"  long lists FP32 vs FP64 rel err {err:.2e}")
+    assert err < 1e-5
