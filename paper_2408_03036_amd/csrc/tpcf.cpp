@@ -700,6 +700,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         b.inv_boxf = (float)(1.0 / h->g.box);
         b.item_start = P<int>(h->d_istart);
         b.item_cell = P<int>(h->d_icell);
+        b.slot_stretch = (double)h->npts >= 12.0 * (double)h->ncat * h->g.ncell ? 1 : 0;
         {
             // work items of the catalogues holding the chunk's primaries
             int c0 = 0, c1 = 0;

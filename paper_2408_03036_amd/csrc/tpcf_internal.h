@@ -106,6 +106,7 @@ struct BinArgs {
     const int* item_start;   // [ncat*ncell+1] first work item of each cell
     const int* item_cell;    // [items] cell of each work item
     int64_t item_lo, item_hi;// work items of the catalogues holding the chunk's primaries
+    int slot_stretch;        // cells of 12+ points on average: spread list regions (see k_pair_bin)
 };
 constexpr int kSlots = 256;  // list allocation cursors (each on its own 128-byte line)
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);

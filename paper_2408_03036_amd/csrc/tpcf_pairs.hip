@@ -150,7 +150,7 @@ struct ItemCtx {
     int64_t cs, cstart;     // first primary of this wavefront's group, catalogue start
     uint32_t cst, mask;
     int cshift, cx, cy, cz, wave, lane, ng;
-    int slot;               // allocation region: (work item, wavefront) spread over all kSlots
+    int slot;               // allocation region of this wavefront
 };
 
 // One sweep over the item's candidates. SWEEP 0 counts the hits of every
@@ -363,9 +363,15 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
         first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
         last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
     }
-    // consecutive (item, wavefront) pairs take consecutive regions, so every
-    // region serves about the same number of primaries whatever the cell sizes
-    c.slot = (int)((item * kNW + c.wave) % kSlots);
+    // The region follows the wavefront's first primary pl0 (chunk-relative),
+    // which spreads evenly when cells are small (items rarely full). With
+    // full items of 16 primaries (large cells) that would use only a quarter
+    // of the regions; there pl0 is stretched by a quarter, pl0 + 4 floor(pl0 / 16),
+    // which steps through all of them (by 20 per item).
+    {
+        const int64_t pl0 = max(first, a.p_begin) + c.wave - a.p_begin;
+        c.slot = (int)((a.slot_stretch ? pl0 + 4 * (pl0 >> 4) : pl0) % kSlots);
+    }
     c.cs = max(first, a.p_begin);
     const int64_t ce = min(last, a.p_end);
     if (c.cs >= ce) return;
