@@ -40,11 +40,9 @@ namespace {
 // zero separation. Periodic shifts come from the cell geometry (equal to the
 // minimum image for any pair inside the shells) or, in single-cell mode,
 // from rint.
-// Takes its few parameters by value: out of line, the rare call costs the
-// hot loop no registers and copies no argument block to scratch.
 template <bool SINGLE>
-__device__ __noinline__ int exact_bin_t(const double4 P, const double4 Q, int wbits, double box, int nb,
-                                        const double* e2) {
+__device__ __forceinline__ int exact_bin_t(const double4 P, const double4 Q, int wbits, double box, int nb,
+                                           const double* e2) {
 #pragma clang fp contract(off)
     double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
     if constexpr (SINGLE) {
@@ -66,11 +64,14 @@ __device__ __noinline__ int exact_bin_t(const double4 P, const double4 Q, int wb
 }
 
 // Exact bin of the pair (primary p, candidate with list entry `entry`) for a
-// pair inside an FP32 guard band. Out of line: it is rare.
+// pair inside an FP32 guard band (rare). Inlined: it is evaluated once per
+// tile, after the tests, where its registers are free; as a call it would
+// cost the kernel the callee-saved registers and make every tile wait for
+// its pending loads before the tests.
 template <bool SINGLE>
-__device__ __noinline__ int exact_pair(const double4* pd, int64_t p, int64_t cstart, uint32_t entry,
-                                       uint32_t mask, int cshift, int cx, int cy, int cz, int k, int nc,
-                                       double box, int nb, const double* e2) {
+__device__ __forceinline__ int exact_pair(const double4* pd, int64_t p, int64_t cstart, uint32_t entry,
+                                          uint32_t mask, int cshift, int cx, int cy, int cz, int k, int nc,
+                                          double box, int nb, const double* e2) {
     const int64_t j = cstart + (int64_t)(entry & mask);
     const int wb = SINGLE ? 0 : wrap_bits_of((int)(entry >> cshift), cx, cy, cz, k, nc);
     return exact_bin_t<SINGLE>(pd[p], pd[j], wb, box, nb, e2);
@@ -80,7 +81,6 @@ constexpr int kNW = 4;                     // wavefronts per workgroup
 constexpr int kGM = kItemPrims / kNW;      // primaries per wavefront
 constexpr int kTile = 256;                 // candidates per LDS tile
 constexpr int kUT = kTile / 64;            // tile candidates per lane
-constexpr int kStage = (kTile + 64 * kNW - 1) / (64 * kNW); // candidates each thread stages per tile
 constexpr uint32_t kNoBase = 0xffffffffu;
 static_assert(kGM * kNW == kItemPrims, "item size");
 
@@ -111,27 +111,32 @@ __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, 
         st.zo = rc.w;
         st.code = S.code[r] & 0xffff;
         st.q = pf[st.j];
-        st.w = REC ? (pw ? pw[st.j] : 1.f) : 0.f;
+        // unit weights are applied when the candidate is stored: the weight
+        // register is only ever written by its load
+        if (REC && pw) st.w = pw[st.j];
     }
 }
 
 // Writes a staged candidate in the home cell's frame, (x, y, z, w), and its
-// list entry = catalogue-relative index | stencil code << cshift.
-template <bool SINGLE>
+// list entry = catalogue-relative index | stencil code << cshift. Also called
+// for an empty slot (past the last candidate, never tested): the write is
+// then harmless, and being unconditional it keeps the wait for the slot's
+// load on every path.
+template <bool SINGLE, bool REC>
 __device__ __forceinline__ void stage_store(const Staged& st, float4* dst, uint32_t* dent, uint32_t cst,
-                                            int cshift, float hf) {
-    if (!st.ok) return;
+                                            int cshift, float hf, bool weighted) {
+    const float w = REC ? (weighted ? st.w : 1.f) : 0.f;
     float4 v;
     uint32_t e;
     if constexpr (SINGLE) {
-        v = make_float4(st.q.x, st.q.y, st.q.z, st.w);
+        v = make_float4(st.q.x, st.q.y, st.q.z, w);
         e = st.j - cst;
     } else {
         const int oz = (int)(st.q.w + st.zo);
         v.x = st.q.x + st.sx;
         v.y = st.q.y + st.sy;
         v.z = fmaf((float)oz, hf, st.q.z);
-        v.w = st.w;
+        v.w = w;
         e = (st.j - cst) | ((uint32_t)(st.code + oz) << cshift);
     }
     *dst = v;
@@ -153,12 +158,58 @@ struct ItemCtx {
     int slot;               // allocation region of this wavefront
 };
 
+// Separation of a staged candidate from a primary, in the FP32 frame of the
+// tests and the records.
+template <bool SINGLE>
+__device__ __forceinline__ void separation(const BinArgs& a, const float4 q, float px, float py, float pz,
+                                           float& dx, float& dy, float& dz) {
+    dx = q.x - px;
+    dy = q.y - py;
+    dz = q.z - pz;
+    if constexpr (SINGLE) {
+        dx -= a.g.boxf * rintf(dx * a.inv_boxf);
+        dy -= a.g.boxf * rintf(dy * a.inv_boxf);
+        dz -= a.g.boxf * rintf(dz * a.inv_boxf);
+    }
+}
+
+// Records a hit of primary g in bin b (b < 0: none): SWEEP 0 counts it;
+// SWEEP 1 and 2 take the next slot of the bin and write the list entry, or
+// with REC the record (dx, dy, dz, w_j); SWEEP 2 drops (but still counts) a
+// hit beyond the end of the bin's predicted region.
+template <int SWEEP, bool REC>
+__device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int g, int b, uint32_t base_g,
+                                        float dx, float dy, float dz, float w, uint32_t entry) {
+    if constexpr (SWEEP == 0) {
+        if (b >= 0) atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
+    } else if (b >= 0 && base_g != kNoBase) {
+        // the LDS unit serves the lanes of one atomic in a fixed order, so
+        // the lists are the same on every run
+        const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
+        if (SWEEP == 2 && pos >= c.capoff[b + 1]) return;
+        if constexpr (REC) {
+            a.rec[base_g + pos] = make_float4(dx, dy, dz, w);
+        } else {
+            a.list[base_g + pos] = entry;
+        }
+    }
+}
+
 // One sweep over the item's candidates. SWEEP 0 counts the hits of every
 // (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
 // bin), the offsets having been prepared in cnt; SWEEP 2 does the same inside
 // the predicted bin regions capoff, and drops (but still counts) the hits
 // beyond a region's end. A hit is written as a list entry, or with REC as the
 // record (dx, dy, dz, w_j) that the FP32 harmonic pass streams.
+//
+// Each thread stages one slot of the next tile: its load is issued before the
+// tests and its LDS write follows them, so the tile's loads are covered by
+// the tests and the only wait of a tile is the one of that write (loads and
+// stores complete in order, so it also drains the tile's hit stores).
+//
+// A pair inside the guard band of an edge is only marked during the tests
+// (one bit per (tile slot, primary) of the lane) and binned exactly after
+// them, outside the test loop.
 template <int SWEEP, bool SINGLE, bool UNIFORM, bool REC>
 __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, const float (&px)[kGM],
                                           const float (&py)[kGM], const float (&pz)[kGM],
@@ -168,32 +219,23 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
     const float lo2 = T.e2f[0] - T.guard[0];
     const float hi2 = T.e2f[a.nb] + T.guard[a.nb];
     const unsigned nbu = (unsigned)a.nb;
-    // thread x stages tile slots x, x + 64 kNW, ... below kTile
-    Staged st[kStage];
-#pragma unroll
-    for (int s = 0; s < kStage; ++s) {
-        st[s].r = 0;
-        st[s].ok = false;
-        const int i = s * 64 * kNW + threadIdx.x;
-        if (i < kTile) {
-            stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, i, a.pf, a.pw);
-            stage_store<SINGLE>(st[s], c.tiles + i, c.tent + i, c.cst, c.cshift, a.g.hf);
-        }
-    }
+    // thread x stages tile slot x
+    static_assert(kTile == 64 * kNW, "one staging slot per thread");
+    Staged st;
+    st.r = 0;
+    stage_load<SINGLE, REC>(st, *c.S, c.np, c.total, (int)threadIdx.x, a.pf, a.pw);
+    stage_store<SINGLE, REC>(st, c.tiles + threadIdx.x, c.tent + threadIdx.x, c.cst, c.cshift, a.g.hf,
+                             a.pw != nullptr);
     __syncthreads();
     int buf = 0;
     for (int t = 0; t < c.total; t += kTile) {
         const float4* cur = c.tiles + buf * kTile;
         const uint32_t* cure = c.tent + buf * kTile;
         const bool more = t + kTile < c.total;
-        if (more) {
-#pragma unroll
-            for (int s = 0; s < kStage; ++s)
-                if (s * 64 * kNW + (int)threadIdx.x < kTile)
-                    stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, t + kTile + s * 64 * kNW + (int)threadIdx.x,
-                                            a.pf, a.pw);
-        }
+        if (more) stage_load<SINGLE, REC>(st, *c.S, c.np, c.total, t + kTile + (int)threadIdx.x, a.pf, a.pw);
         const int nt = min(kTile, c.total - t);
+        uint32_t nearbits = 0;
+        static_assert(kUT * kGM <= 32, "near-edge marks");
 #pragma unroll 2
         for (int u = 0; u < kUT; ++u) {
             const int i = u * 64 + c.lane;
@@ -203,12 +245,8 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
 #pragma unroll
             for (int g = 0; g < kGM; ++g) {
                 if (g >= c.ng) break;
-                float dx = q.x - px[g], dy = q.y - py[g], dz = q.z - pz[g];
-                if constexpr (SINGLE) {
-                    dx -= a.g.boxf * rintf(dx * a.inv_boxf);
-                    dy -= a.g.boxf * rintf(dy * a.inv_boxf);
-                    dz -= a.g.boxf * rintf(dz * a.inv_boxf);
-                }
+                float dx, dy, dz;
+                separation<SINGLE>(a, q, px[g], py[g], pz[g], dx, dy, dz);
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 int bb;
                 bool near;
@@ -229,33 +267,36 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
                         }
                     }
                 }
-                int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
-                if (valid && near) {
-                    b = exact_pair<SINGLE>(a.pd, c.cs + c.wave + kNW * g, c.cstart, entry, c.mask, c.cshift,
-                                           c.cx, c.cy, c.cz, a.g.k, a.g.nc, a.g.box, a.nb, T.e2);
+                const int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
+                if (__ballot(valid && near) != 0ull) {
+                    if (valid && near) nearbits |= 1u << (u * kGM + g);
                 }
-                if constexpr (SWEEP == 0) {
-                    if (b >= 0) atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
-                } else if (b >= 0 && base[g] != kNoBase) {
-                    // the LDS unit serves the lanes of one atomic in a fixed
-                    // order, so the lists are the same on every run
-                    const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
-                    if (SWEEP == 2 && pos >= c.capoff[b + 1]) continue;
-                    if constexpr (REC) {
-                        a.rec[base[g] + pos] = make_float4(dx, dy, dz, q.w);
-                    } else {
-                        a.list[base[g] + pos] = entry;
-                    }
-                }
+                put_hit<SWEEP, REC>(a, c, g, b, base[g], dx, dy, dz, q.w, entry);
             }
         }
-        if (more) {
+        // the next tile's slot (written also after the last tile: the other
+        // buffer is then unused)
+        stage_store<SINGLE, REC>(st, c.tiles + (buf ^ 1) * kTile + threadIdx.x,
+                                 c.tent + (buf ^ 1) * kTile + threadIdx.x, c.cst, c.cshift, a.g.hf, a.pw != nullptr);
+        // the marked near-edge pairs, binned exactly (rare)
+        if (__ballot(nearbits != 0u) != 0ull) {
 #pragma unroll
-            for (int s = 0; s < kStage; ++s)
-                if (s * 64 * kNW + (int)threadIdx.x < kTile)
-                    stage_store<SINGLE>(st[s], c.tiles + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x,
-                                        c.tent + (buf ^ 1) * kTile + s * 64 * kNW + threadIdx.x, c.cst, c.cshift,
-                                        a.g.hf);
+            for (int g = 0; g < kGM; ++g) {
+                // bits u kGM + g of this primary
+                uint32_t m = nearbits & (0x11111111u << g);
+                while (m != 0u) {
+                    const int bit = __builtin_ctz(m);
+                    m &= m - 1u;
+                    const int i = (bit / kGM) * 64 + c.lane;
+                    const float4 q = cur[i];
+                    const uint32_t entry = cure[i];
+                    float dx, dy, dz;
+                    separation<SINGLE>(a, q, px[g], py[g], pz[g], dx, dy, dz);
+                    const int b = exact_pair<SINGLE>(a.pd, c.cs + c.wave + kNW * g, c.cstart, entry, c.mask,
+                                                     c.cshift, c.cx, c.cy, c.cz, a.g.k, a.g.nc, a.g.box, a.nb, T.e2);
+                    put_hit<SWEEP, REC>(a, c, g, b, base[g], dx, dy, dz, q.w, entry);
+                }
+            }
         }
         __syncthreads();
         buf ^= 1;
@@ -400,10 +441,11 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
         px[g] = py[g] = pz[g] = 0.f;
         base[g] = kNoBase;
         if (g < c.ng) {
+            // uniform over the wavefront: scalar registers
             const float4 P = a.pf[c.cs + c.wave + kNW * g];
-            px[g] = P.x;
-            py[g] = P.y;
-            pz[g] = P.z;
+            px[g] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.x)));
+            py[g] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.y)));
+            pz[g] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.z)));
         }
     }
 
