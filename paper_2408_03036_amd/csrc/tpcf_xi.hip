@@ -52,7 +52,7 @@ static_assert(kXG * kXW == kItemPrims, "item size");
 // mu is exactly -mu. Periodic shifts come from the stencil code (equal to the
 // minimum image inside the shells) or, in single-cell mode, from rint.
 template <bool SINGLE>
-__device__ __noinline__ int2 exact_xi_t(const double4 P, const double4 Q, int wbits, double box, int nb,
+__device__ __forceinline__ int2 exact_xi_t(const double4 P, const double4 Q, int wbits, double box, int nb,
                                         const double* e2, int nmu, double hmu) {
 #pragma clang fp contract(off)
     double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
@@ -80,8 +80,11 @@ __device__ __noinline__ int2 exact_xi_t(const double4 P, const double4 Q, int wb
     return make_int2(b * nmu + kbin(mu), b * nmu + kbin(-mu));
 }
 
+// Inlined, and evaluated after a tile's tests for the pairs they marked: as
+// a call inside the test loop it would cost the kernel the callee-saved
+// registers and make every tile wait for its pending loads.
 template <bool SINGLE>
-__device__ __noinline__ int2 exact_xi_pair(const double4* pd, int64_t p, uint32_t entry, uint32_t mask,
+__device__ __forceinline__ int2 exact_xi_pair(const double4* pd, int64_t p, uint32_t entry, uint32_t mask,
                                            int cshift, int cx, int cy, int cz, int k, int nc, double box,
                                            int nb, const double* e2, int nmu, double hmu) {
     const int64_t j = (int64_t)(entry & mask);
@@ -115,10 +118,12 @@ __device__ __forceinline__ void xstage_load(XStaged& st, const Pieces& S, int to
     }
 }
 
+// Also called for an empty slot (past the last candidate, never tested): the
+// write is then harmless, and being unconditional it keeps the wait for the
+// slot's load on every path.
 template <bool SINGLE>
 __device__ __forceinline__ void xstage_store(const XStaged& st, float4* dst, uint32_t* dent, int cshift,
                                              float hf) {
-    if (!st.ok) return;
     if constexpr (SINGLE) {
         *dst = make_float4(st.q.x, st.q.y, st.q.z, 0.f);
         *dent = st.j;
@@ -226,25 +231,23 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
         for (int g = 0; g < kXG; ++g) {
             px[g] = py[g] = pz[g] = 0.f;
             if (g < ng) {
+                // uniform over the wavefront: scalar registers
                 const float4 P = a.pf[first + wave + kXW * g];
-                px[g] = P.x;
-                py[g] = P.y;
-                pz[g] = P.z;
+                px[g] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.x)));
+                py[g] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.y)));
+                pz[g] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.z)));
             }
         }
 
-        // thread x stages tile slots x, x + 256, ... below kXTile
-        XStaged st[kXStage];
-        const bool stager = (int)threadIdx.x < kXTile;
-#pragma unroll
-        for (int s = 0; s < kXStage; ++s) {
-            st[s].r = 0;
-            st[s].ok = false;
-            const int i = s * 64 * kXW + threadIdx.x;
-            if (i < kXTile) {
-                xstage_load(st[s], S, total, i, a.pf);
-                xstage_store<SINGLE>(st[s], tiles + i, tent + i, cshift, a.g.hf);
-            }
+        // the first kXTile / 64 wavefronts stage, thread x tile slot x: its
+        // load is issued before the tests and its LDS write follows them
+        static_assert(kXStage == 1 && kXTile % 64 == 0, "one staging slot per staging thread");
+        XStaged st;
+        st.r = 0;
+        const bool stager = wave < kXTile / 64;
+        if (stager) {
+            xstage_load(st, S, total, (int)threadIdx.x, a.pf);
+            xstage_store<SINGLE>(st, tiles + threadIdx.x, tent + threadIdx.x, cshift, a.g.hf);
         }
         __syncthreads();
         int buf = 0;
@@ -252,13 +255,10 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
             const float4* cur = tiles + buf * kXTile;
             const uint32_t* cure = tent + buf * kXTile;
             const bool more = t + kXTile < total;
-            if (more && stager) {
-#pragma unroll
-                for (int s = 0; s < kXStage; ++s)
-                    if (s * 64 * kXW + (int)threadIdx.x < kXTile)
-                        xstage_load(st[s], S, total, t + kXTile + s * 64 * kXW + (int)threadIdx.x, a.pf);
-            }
+            if (more && stager) xstage_load(st, S, total, t + kXTile + (int)threadIdx.x, a.pf);
             const int nt = min(kXTile, total - t);
+            uint32_t nearbits = 0;
+            static_assert(kXUT * kXG <= 32, "near-edge marks");
 #pragma unroll 2
             for (int u = 0; u < kXUT; ++u) {
                 const int i = u * 64 + lane;
@@ -307,27 +307,41 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
                     const float gt = fmaf(a.gmu_a, rinv, a.gmu_b);
                     near |= !(ft >= gt && ft <= 1.0f - gt);  // also catches r = 0 (inf / nan)
                     near |= both && !(ftr >= gt && ftr <= 1.0f - gt);
-                    int2 idx;
-                    if (near) {
-                        idx = exact_xi_pair<SINGLE>(a.pd, first + wave + kXW * g, entry, mask, cshift, cx, cy, cz,
-                                                    a.g.k, a.g.nc, a.g.box, a.nb, X.e2, a.nmu, a.hmu);
-                    } else {
-                        const int row = bb * a.nmu, top = a.nmu - 1;
-                        idx = make_int2(row + min(max((int)fk, 0), top), row + min(max((int)fkr, 0), top));
+                    // a pair near an edge is only marked here
+                    if (__ballot(near) != 0ull) {
+                        if (near) nearbits |= 1u << (u * kXG + g);
                     }
-                    if (idx.x >= 0) {
-                        atomicAdd(hist + idx.x, 1u);
-                        if (both) atomicAdd(hist + idx.y, 1u);
+                    if (!near) {
+                        const int row = bb * a.nmu, top = a.nmu - 1;
+                        atomicAdd(hist + row + min(max((int)fk, 0), top), 1u);
+                        if (both) atomicAdd(hist + row + min(max((int)fkr, 0), top), 1u);
                     }
                 }
             }
-            if (more && stager) {
+            // the next tile's slot (written also after the last tile: the
+            // other buffer is then unused)
+            if (stager)
+                xstage_store<SINGLE>(st, tiles + (buf ^ 1) * kXTile + threadIdx.x,
+                                     tent + (buf ^ 1) * kXTile + threadIdx.x, cshift, a.g.hf);
+            // the marked pairs, binned exactly (rare)
+            if (__ballot(nearbits != 0u) != 0ull) {
 #pragma unroll
-                for (int s = 0; s < kXStage; ++s)
-                    if (s * 64 * kXW + (int)threadIdx.x < kXTile)
-                        xstage_store<SINGLE>(st[s], tiles + (buf ^ 1) * kXTile + s * 64 * kXW + threadIdx.x,
-                                             tent + (buf ^ 1) * kXTile + s * 64 * kXW + threadIdx.x, cshift,
-                                             a.g.hf);
+                for (int g = 0; g < kXG; ++g) {
+                    uint32_t m = nearbits & (0x11111111u << g);  // bits u kXG + g
+                    while (m != 0u) {
+                        const int bit = __builtin_ctz(m);
+                        m &= m - 1u;
+                        const uint32_t entry = cure[(bit / kXG) * 64 + lane];
+                        const bool both = !SINGLE && (entry >> cshift) != home_code;
+                        const int2 idx = exact_xi_pair<SINGLE>(a.pd, first + wave + kXW * g, entry, mask, cshift, cx,
+                                                               cy, cz, a.g.k, a.g.nc, a.g.box, a.nb, X.e2, a.nmu,
+                                                               a.hmu);
+                        if (idx.x >= 0) {
+                            atomicAdd(hist + idx.x, 1u);
+                            if (both) atomicAdd(hist + idx.y, 1u);
+                        }
+                    }
+                }
             }
             __syncthreads();
             buf ^= 1;
