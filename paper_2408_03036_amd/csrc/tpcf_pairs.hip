@@ -643,40 +643,39 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         n = a.cnt[pl * a.nb + b];
         off = a.boff[pl * a.nb + b];
     }
-    if constexpr (sizeof(T) == 4 && (LMAX >= 8 || G != 0)) {
-        // FP32: the binning pass wrote each hit as (dx, dy, dz, w_j); records
-        // two hits ahead are in flight while a hit is accumulated.
-        const float4* rec = a.rec + off;
-        float4 r0 = n > 0 ? rec[0] : make_float4(1.f, 0.f, 0.f, 0.f);
-        float4 r1 = n > 1 ? rec[1] : make_float4(1.f, 0.f, 0.f, 0.f);
-        for (uint32_t t = 0; t < n; ++t) {
-            const float4 r2 = t + 2 < n ? rec[t + 2] : make_float4(1.f, 0.f, 0.f, 0.f);
-            const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the binning pass wrote each hit as (dx, dy, dz, w_j). Two
+        // sets of K records per lane in ping-pong: each half of an iteration
+        // first refills the other set with the next K records, then
+        // accumulates its own set, loaded one half earlier. The loads are
+        // unconditional (at a clamped index past the end of the list), so the
+        // loads in flight are the same on every path: the wait before a set
+        // is used covers exactly that set, loaded a whole half (K hits of
+        // arithmetic) before. (Conditional loads, or rotating registers,
+        // would make every hit wait for the newest load.)
+        constexpr int K = LMAX <= 4 ? 4 : 2;
+        // an empty list reads the first record of the buffer (not accumulated)
+        const float4* rec = n > 0 ? a.rec + off : a.rec;
+        const uint32_t last = n > 0 ? n - 1 : 0;
+        float4 qa[K], qb[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) qa[i] = rec[min((uint32_t)i, last)];
+        auto hit = [&](const float4 q) {
+            const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
             const float inv = __builtin_amdgcn_rsqf(d2);
-            add_hit<T, LMAX, G, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
-            r0 = r1;
-            r1 = r2;
-        }
-    } else if constexpr (sizeof(T) == 4) {
-        // Low lmax: too little arithmetic per hit to cover the memory latency
-        // with two records in flight, so a ring of D records (slot i holds
-        // records t + i; the record D ahead is loaded into the slot just read).
-        constexpr int D = LMAX <= 4 ? 8 : 4;
-        const float4* rec = a.rec + off;
-        float4 q[D];
+            add_hit<T, LMAX, G, UNIT>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+        };
+        for (uint32_t t = 0; t < n; t += 2 * K) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) q[i] = (uint32_t)i < n ? rec[i] : make_float4(1.f, 0.f, 0.f, 0.f);
-        for (uint32_t t = 0; t < n; t += D) {
+            for (int i = 0; i < K; ++i) qb[i] = rec[min(t + K + i, last)];
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const float4 r0 = q[i];
-                if (t + i + D < n) q[i] = rec[t + i + D];
-                if (t + i < n) {
-                    const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
-                    const float inv = __builtin_amdgcn_rsqf(d2);
-                    add_hit<T, LMAX, G, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
-                }
-            }
+            for (int i = 0; i < K; ++i)
+                if (t + i < n) hit(qa[i]);
+#pragma unroll
+            for (int i = 0; i < K; ++i) qa[i] = rec[min(t + 2 * K + i, last)];
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (t + K + i < n) hit(qb[i]);
         }
     } else {
         // FP64: list entries two hits ahead and the point one hit ahead.
@@ -751,14 +750,30 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
 #pragma unroll
     for (int i = 0; i < AC::NS; ++i) acc.s[i] = 0.f;
     const uint32_t n = a.cnt[pl * a.nb + b];
-    const float4* rec = a.rec + a.boff[pl * a.nb + b];
-    float4 r0 = (uint32_t)lane < n ? rec[lane] : make_float4(1.f, 0.f, 0.f, 0.f);
-    for (uint32_t t = lane; t < n; t += 64) {
-        const float4 r1 = t + 64 < n ? rec[t + 64] : make_float4(1.f, 0.f, 0.f, 0.f);
-        const float d2 = r0.x * r0.x + r0.y * r0.y + r0.z * r0.z;
+    // the same ping-pong of unconditional loads as the lane-per-list kernel,
+    // over blocks of 64 consecutive records (n is uniform over the wavefront)
+    constexpr int K = 2;
+    const float4* rec = n > 0 ? a.rec + a.boff[pl * a.nb + b] : a.rec;
+    const uint32_t last = n > 0 ? n - 1 : 0;
+    float4 qa[K], qb[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) qa[i] = rec[min((uint32_t)(64 * i + lane), last)];
+    auto hit = [&](const float4 q) {
+        const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
         const float inv = __builtin_amdgcn_rsqf(d2);
-        add_hit<float, LMAX, 0, UNIT>(acc, r0.x * inv, r0.y * inv, r0.z * inv, r0.w);
-        r0 = r1;
+        add_hit<float, LMAX, 0, UNIT>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+    };
+    for (uint32_t t0 = 0; t0 < n; t0 += 128 * K) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) qb[i] = rec[min(t0 + 64 * (K + i) + lane, last)];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (t0 + 64 * i + lane < n) hit(qa[i]);
+#pragma unroll
+        for (int i = 0; i < K; ++i) qa[i] = rec[min(t0 + 64 * (2 * K + i) + lane, last)];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (t0 + 64 * (K + i) + lane < n) hit(qb[i]);
     }
     // every lane ends with the total of every value
 #pragma unroll
