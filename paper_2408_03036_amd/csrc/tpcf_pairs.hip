@@ -29,6 +29,8 @@
 // r^2 = dx*dx + dy*dy + dz*dz against the squared edges. The FP32 path bins in
 // single precision from cell-relative coordinates and re-evaluates in FP64 the
 // rare pairs that fall inside a guard band around an edge.
+#include <type_traits>
+
 #include "tpcf_cells.h"
 
 namespace tpcf {
@@ -81,6 +83,15 @@ constexpr int kNW = 4;                     // wavefronts per workgroup
 constexpr int kGM = kItemPrims / kNW;      // primaries per wavefront
 constexpr int kTile = 256;                 // candidates per LDS tile
 constexpr int kUT = kTile / 64;            // tile candidates per lane
+// staging: a thread stages kStage slots of each tile (all threads when the
+// tile holds at least one slot per thread, else the first kTile / 64 waves)
+constexpr int kStage = kTile >= 64 * kNW ? kTile / (64 * kNW) : 1;
+static_assert(kTile % 64 == 0 && (kTile < 64 * kNW || kTile % (64 * kNW) == 0), "tile shape");
+// near-edge marks of a lane: bit u kGM + g for (tile slot u, primary g);
+// kNearPrimary has the bits of primary 0
+using NearMask = std::conditional_t<(kUT * kGM > 32), uint64_t, uint32_t>;
+static_assert(kUT * kGM <= 64 && kGM == 4, "near-edge marks");
+constexpr NearMask kNearPrimary = (NearMask)0x1111111111111111ull;
 constexpr uint32_t kNoBase = 0xffffffffu;
 static_assert(kGM * kNW == kItemPrims, "item size");
 
@@ -219,23 +230,35 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
     const float lo2 = T.e2f[0] - T.guard[0];
     const float hi2 = T.e2f[a.nb] + T.guard[a.nb];
     const unsigned nbu = (unsigned)a.nb;
-    // thread x stages tile slot x
-    static_assert(kTile == 64 * kNW, "one staging slot per thread");
-    Staged st;
-    st.r = 0;
-    stage_load<SINGLE, REC>(st, *c.S, c.np, c.total, (int)threadIdx.x, a.pf, a.pw);
-    stage_store<SINGLE, REC>(st, c.tiles + threadIdx.x, c.tent + threadIdx.x, c.cst, c.cshift, a.g.hf,
-                             a.pw != nullptr);
+    // thread x stages tile slots x + 64 kNW s (s < kStage); the staging
+    // waves are uniform, so their branches are scalar
+    const bool stager = kTile >= 64 * kNW || c.wave < kTile / 64;
+    Staged st[kStage];
+#pragma unroll
+    for (int s = 0; s < kStage; ++s) st[s].r = 0;
+    if (stager) {
+#pragma unroll
+        for (int s = 0; s < kStage; ++s)
+            stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, (int)threadIdx.x + 64 * kNW * s, a.pf, a.pw);
+#pragma unroll
+        for (int s = 0; s < kStage; ++s)
+            stage_store<SINGLE, REC>(st[s], c.tiles + threadIdx.x + 64 * kNW * s, c.tent + threadIdx.x + 64 * kNW * s,
+                                     c.cst, c.cshift, a.g.hf, a.pw != nullptr);
+    }
     __syncthreads();
     int buf = 0;
     for (int t = 0; t < c.total; t += kTile) {
         const float4* cur = c.tiles + buf * kTile;
         const uint32_t* cure = c.tent + buf * kTile;
         const bool more = t + kTile < c.total;
-        if (more) stage_load<SINGLE, REC>(st, *c.S, c.np, c.total, t + kTile + (int)threadIdx.x, a.pf, a.pw);
+        if (more && stager) {
+#pragma unroll
+            for (int s = 0; s < kStage; ++s)
+                stage_load<SINGLE, REC>(st[s], *c.S, c.np, c.total, t + kTile + (int)threadIdx.x + 64 * kNW * s, a.pf,
+                                        a.pw);
+        }
         const int nt = min(kTile, c.total - t);
-        uint32_t nearbits = 0;
-        static_assert(kUT * kGM <= 32, "near-edge marks");
+        NearMask nearbits = 0;
 #pragma unroll 2
         for (int u = 0; u < kUT; ++u) {
             const int i = u * 64 + c.lane;
@@ -269,24 +292,29 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
                 }
                 const int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
                 if (__ballot(valid && near) != 0ull) {
-                    if (valid && near) nearbits |= 1u << (u * kGM + g);
+                    if (valid && near) nearbits |= (NearMask)1 << (u * kGM + g);
                 }
                 put_hit<SWEEP, REC>(a, c, g, b, base[g], dx, dy, dz, q.w, entry);
             }
         }
         // the next tile's slot (written also after the last tile: the other
         // buffer is then unused)
-        stage_store<SINGLE, REC>(st, c.tiles + (buf ^ 1) * kTile + threadIdx.x,
-                                 c.tent + (buf ^ 1) * kTile + threadIdx.x, c.cst, c.cshift, a.g.hf, a.pw != nullptr);
+        if (stager) {
+#pragma unroll
+            for (int s = 0; s < kStage; ++s)
+                stage_store<SINGLE, REC>(st[s], c.tiles + (buf ^ 1) * kTile + threadIdx.x + 64 * kNW * s,
+                                         c.tent + (buf ^ 1) * kTile + threadIdx.x + 64 * kNW * s, c.cst, c.cshift,
+                                         a.g.hf, a.pw != nullptr);
+        }
         // the marked near-edge pairs, binned exactly (rare)
-        if (__ballot(nearbits != 0u) != 0ull) {
+        if (__ballot(nearbits != 0) != 0ull) {
 #pragma unroll
             for (int g = 0; g < kGM; ++g) {
                 // bits u kGM + g of this primary
-                uint32_t m = nearbits & (0x11111111u << g);
-                while (m != 0u) {
-                    const int bit = __builtin_ctz(m);
-                    m &= m - 1u;
+                NearMask m = nearbits & (kNearPrimary << g);
+                while (m != 0) {
+                    const int bit = sizeof(NearMask) == 8 ? __builtin_ctzll(m) : __builtin_ctz((uint32_t)m);
+                    m &= m - 1;
                     const int i = (bit / kGM) * 64 + c.lane;
                     const float4 q = cur[i];
                     const uint32_t entry = cure[i];
@@ -678,23 +706,23 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
                 if (t + K + i < n) hit(qb[i]);
         }
     } else {
-        // FP64: list entries two hits ahead and the point one hit ahead.
-        int64_t cstart = 0;
-        double4 P64 = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (active) {
-            cstart = a.pt_off[a.catid[p]];
-            P64 = a.pd[p];
-        }
+        // FP64: the lane gathers its neighbours through the list entries,
+        // with the same ping-pong of unconditional loads as the FP32 path in
+        // two stages: a set's entries are loaded one half before its points
+        // are gathered, and the points one half before they are accumulated.
+        // A slot past the end of the list gathers the primary itself (not
+        // accumulated), so every address is valid.
+        constexpr int K = 2;
+        const int64_t pself = active ? p : a.p_begin;
+        const int64_t cstart = a.pt_off[a.catid[pself]];
+        const double4 P64 = a.pd[pself];
         const uint32_t mask = a.g.idx_mask;
-        uint32_t e0 = n > 0 ? a.list[off] : 0u;
-        uint32_t e1 = n > 1 ? a.list[off + 1] : 0u;
-        double4 d0 = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (n > 0) d0 = a.pd[cstart + (int64_t)(e0 & mask)];
-        for (uint32_t t = 0; t < n; ++t) {
-            const uint32_t e2 = t + 2 < n ? a.list[off + t + 2] : 0u;
-            double4 d1 = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (t + 1 < n) d1 = a.pd[cstart + (int64_t)(e1 & mask)];
-            double dx = d0.x - P64.x, dy = d0.y - P64.y, dz = d0.z - P64.z;
+        const uint32_t* lst = n > 0 ? a.list + off : a.list;
+        const uint32_t last = n > 0 ? n - 1 : 0;
+        auto entry = [&](uint32_t r) { return lst[min(r, last)]; };
+        auto gather = [&](uint32_t r, uint32_t e) { return a.pd[r < n ? cstart + (int64_t)(e & mask) : pself]; };
+        auto hit = [&](const double4 d) {
+            double dx = d.x - P64.x, dy = d.y - P64.y, dz = d.z - P64.z;
             const double L = a.g.box, hL = 0.5 * a.g.box;
             dx = dx > hL ? dx - L : (dx < -hL ? dx + L : dx);
             dy = dy > hL ? dy - L : (dy < -hL ? dy + L : dy);
@@ -703,10 +731,31 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
             double inv = __builtin_amdgcn_rsq(r2);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
-            add_hit<T, LMAX, G, UNIT>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d0.w);
-            e0 = e1;
-            e1 = e2;
-            d0 = d1;
+            add_hit<T, LMAX, G, UNIT>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d.w);
+        };
+        uint32_t ea[K], eb[K];
+        double4 da[K], db[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) ea[i] = entry((uint32_t)i);
+#pragma unroll
+        for (int i = 0; i < K; ++i) da[i] = gather((uint32_t)i, ea[i]);
+#pragma unroll
+        for (int i = 0; i < K; ++i) eb[i] = entry((uint32_t)(K + i));
+        for (uint32_t t = 0; t < n; t += 2 * K) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) db[i] = gather(t + K + i, eb[i]);
+#pragma unroll
+            for (int i = 0; i < K; ++i) ea[i] = entry(t + 2 * K + i);
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (t + i < n) hit(da[i]);
+#pragma unroll
+            for (int i = 0; i < K; ++i) da[i] = gather(t + 2 * K + i, ea[i]);
+#pragma unroll
+            for (int i = 0; i < K; ++i) eb[i] = entry(t + 3 * K + i);
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (t + K + i < n) hit(db[i]);
         }
     }
     if (!active) return;
