@@ -90,8 +90,13 @@ static_assert(kTile % 64 == 0 && (kTile < 64 * kNW || kTile % (64 * kNW) == 0), 
 // near-edge marks of a lane: bit u kGM + g for (tile slot u, primary g);
 // kNearPrimary has the bits of primary 0
 using NearMask = std::conditional_t<(kUT * kGM > 32), uint64_t, uint32_t>;
-static_assert(kUT * kGM <= 64 && kGM == 4, "near-edge marks");
-constexpr NearMask kNearPrimary = (NearMask)0x1111111111111111ull;
+static_assert(kUT * kGM <= 64, "near-edge marks");
+constexpr NearMask near_primary_bits() {
+    NearMask m = 0;
+    for (int u = 0; u < kUT; ++u) m |= (NearMask)1 << (u * kGM);
+    return m;
+}
+constexpr NearMask kNearPrimary = near_primary_bits();
 constexpr uint32_t kNoBase = 0xffffffffu;
 static_assert(kGM * kNW == kItemPrims, "item size");
 
