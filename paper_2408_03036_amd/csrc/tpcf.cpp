@@ -522,7 +522,8 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_tmp, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_orig, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pf, sizeof(float4) * N)) != TPCF_OK) return st;
-    if ((st = ensure(h, h->d_pw, sizeof(float) * N)) != TPCF_OK) return st;
+    // 8 floats of padding: the contraction's staging reads 8-wide windows
+    if ((st = ensure(h, h->d_pw, sizeof(float) * (N + 8))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pa, sizeof(float4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pd, sizeof(double4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_perm, sizeof(int) * N)) != TPCF_OK) return st;
@@ -642,7 +643,8 @@ tpcf_status plan_chunks(tpcf_handle h) {
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_cnt, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
-    if ((st = ensure(h, h->d_A, (size_t)h->nb * h->NV * h->ldA * elem)) != TPCF_OK) return st;
+    // 8 elements of padding: the contraction's staging reads 8-wide windows
+    if ((st = ensure(h, h->d_A, ((size_t)h->nb * h->NV * h->ldA + 8) * elem)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_lcursor, sizeof(unsigned long long) * kSlots * 16)) != TPCF_OK) return st;
     // subchunk tables: chunk-relative starts of every chunk, one upload

@@ -510,63 +510,57 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
         iok[u] = it < nitems && c < K;
         ik8[u] = k8;
         ioff[u] = c * KSP + k8;
-        irow[u] = ((int64_t)b * NV + voff + lp) * a.ldA + k8;
+        irow[u] = ((int64_t)b * NV + voff + lp) * a.ldA;
     }
     const int64_t part_stride = (int64_t)nl * a.ldA;
 
-    // loads of step st into registers
+    // Loads of step st into registers: two unconditional 16-byte loads per
+    // item (and two of weights), all in bounds (the operand and the weight
+    // buffers end with 8 elements of padding; an idle item, or one past the
+    // step's primaries, reads the start of its row or of the buffer). The
+    // elements that are not the step's primaries are zeroed when the step is
+    // stored. Unconditional loads keep the count of loads in flight the same
+    // on every path, so that waiting for one step never waits for the next.
     auto load = [&](int st, BfStage<W>& R) {
         const int part = st % parts;
         const int64_t p0 = pa + (int64_t)(st / parts) * KS;
         const int kv = (int)min((int64_t)KS, pb - p0);
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
-            const int k8 = ik8[u];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                R.x[u][e] = 0.f;
-                if constexpr (W) R.w[u][e] = 0.f;
-            }
-            if (!iok[u] || k8 >= kv) continue;
-            const float* src = A + irow[u] + part * part_stride + p0;
-            const float* wsrc = a.pw + a.p_begin + p0 + k8;
-            if (k8 + 8 <= kv) {
-                float4 v0, v1;
-                __builtin_memcpy(&v0, src, 16);
-                __builtin_memcpy(&v1, src + 4, 16);
-                R.x[u][0] = v0.x; R.x[u][1] = v0.y; R.x[u][2] = v0.z; R.x[u][3] = v0.w;
-                R.x[u][4] = v1.x; R.x[u][5] = v1.y; R.x[u][6] = v1.z; R.x[u][7] = v1.w;
-                if constexpr (W) {
-                    __builtin_memcpy(&v0, wsrc, 16);
-                    __builtin_memcpy(&v1, wsrc + 4, 16);
-                    R.w[u][0] = v0.x; R.w[u][1] = v0.y; R.w[u][2] = v0.z; R.w[u][3] = v0.w;
-                    R.w[u][4] = v1.x; R.w[u][5] = v1.y; R.w[u][6] = v1.z; R.w[u][7] = v1.w;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if (k8 + e < kv) {
-                        R.x[u][e] = src[e];
-                        if constexpr (W) R.w[u][e] = wsrc[e];
-                    }
-                }
+            const int kk = ik8[u] < kv ? ik8[u] : 0;
+            const float* src = A + (iok[u] ? irow[u] + part * part_stride + p0 + kk : 0);
+            float4 v0, v1;
+            __builtin_memcpy(&v0, src, 16);
+            __builtin_memcpy(&v1, src + 4, 16);
+            R.x[u][0] = v0.x; R.x[u][1] = v0.y; R.x[u][2] = v0.z; R.x[u][3] = v0.w;
+            R.x[u][4] = v1.x; R.x[u][5] = v1.y; R.x[u][6] = v1.z; R.x[u][7] = v1.w;
+            if constexpr (W) {
+                const float* wsrc = a.pw + a.p_begin + p0 + kk;
+                __builtin_memcpy(&v0, wsrc, 16);
+                __builtin_memcpy(&v1, wsrc + 4, 16);
+                R.w[u][0] = v0.x; R.w[u][1] = v0.y; R.w[u][2] = v0.z; R.w[u][3] = v0.w;
+                R.w[u][4] = v1.x; R.w[u][5] = v1.y; R.w[u][6] = v1.z; R.w[u][7] = v1.w;
             }
         }
     };
-    // converts the registers of a step into BF16 planes of buffer `buf`
-    auto store = [&](int buf, BfStage<W>& R) {
+    // converts the registers of step st into BF16 planes of buffer `buf`
+    auto store = [&](int st, int buf, BfStage<W>& R) {
         uint16_t* base = lds + buf * bufsz;
+        const int64_t p0 = pa + (int64_t)(st / parts) * KS;
+        const int kv = (int)min((int64_t)KS, pb - p0);
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
             if (!istore[u]) continue;
             const int off = ioff[u];
-            float y[8];
-            if constexpr (W) {
+            float x[8], y[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) y[e] = R.x[u][e] * R.w[u][e];
+            for (int e = 0; e < 8; ++e) {
+                const bool ok = iok[u] && ik8[u] + e < kv;
+                x[e] = ok ? R.x[u][e] : 0.f;
+                if constexpr (W) y[e] = ok ? R.x[u][e] * R.w[u][e] : 0.f;
             }
             uint4 pc[NPC];
-            split8<NPC>(R.x[u], pc);
+            split8<NPC>(x, pc);
 #pragma unroll
             for (int q = 0; q < NPC; ++q) *reinterpret_cast<uint4*>(base + q * plane + off) = pc[q];
             if constexpr (W) {
@@ -620,13 +614,13 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
         // step earlier) is converted into the other buffer after them
         BfStage<W> R0, R1;
         load(0, R0);
-        store(0, R0);
+        store(0, 0, R0);
         if (nsteps > 1) load(1, R1);
         __syncthreads();
         auto step = [&](int st, BfStage<W>& Rload, BfStage<W>& Rstore) {
             if (st + 2 < nsteps) load(st + 2, Rload);
             compute(st, st & 1);
-            if (st + 1 < nsteps) store((st + 1) & 1, Rstore);
+            if (st + 1 < nsteps) store(st + 1, (st + 1) & 1, Rstore);
             __syncthreads();
         };
         for (int st = 0; st < nsteps; st += 2) {
@@ -636,14 +630,14 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     } else {
         BfStage<W> R;
         load(0, R);
-        store(0, R);
+        store(0, 0, R);
         __syncthreads();
         for (int st = 0; st < nsteps; ++st) {
             compute(st, 0);
             if (st + 1 < nsteps) {
                 __syncthreads();
                 load(st + 1, R);
-                store(0, R);
+                store(st + 1, 0, R);
             }
             __syncthreads();
         }
