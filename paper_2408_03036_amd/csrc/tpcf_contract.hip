@@ -609,23 +609,19 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     };
 
     if (nbuf == 2) {
-        // two LDS buffers and two register stages: the loads of step st + 2
-        // are issued before the MFMAs of step st, and step st + 1 (loaded a
-        // step earlier) is converted into the other buffer after them
-        BfStage<W> R0, R1;
-        load(0, R0);
-        store(0, 0, R0);
-        if (nsteps > 1) load(1, R1);
+        // two LDS buffers and one register stage: the loads of step st + 1
+        // are issued before the MFMAs of step st and converted into the
+        // other buffer after them (a second register stage, loading two
+        // steps ahead, spilled registers and measured slower)
+        BfStage<W> R;
+        load(0, R);
+        store(0, 0, R);
         __syncthreads();
-        auto step = [&](int st, BfStage<W>& Rload, BfStage<W>& Rstore) {
-            if (st + 2 < nsteps) load(st + 2, Rload);
+        for (int st = 0; st < nsteps; ++st) {
+            if (st + 1 < nsteps) load(st + 1, R);
             compute(st, st & 1);
-            if (st + 1 < nsteps) store(st + 1, (st + 1) & 1, Rstore);
+            if (st + 1 < nsteps) store(st + 1, (st + 1) & 1, R);
             __syncthreads();
-        };
-        for (int st = 0; st < nsteps; st += 2) {
-            step(st, R0, R1);
-            if (st + 1 < nsteps) step(st + 1, R1, R0);
         }
     } else {
         BfStage<W> R;
