@@ -181,6 +181,25 @@ def test_lmax0_exact_counts_every_grid(torch, refine):
         assert err < 1e-12, (PNAME[prec], err)
 
 
+@pytest.mark.parametrize("refine", [1, 2, 3])
+def test_lattice_ties_full_items(torch, refine):
+    """Half-spaced lattice (8 points per unit volume) with edges at multiples
+    of 0.5: most pairs lie exactly on an edge, so nearly every test goes to the
+    exact FP64 decision that follows each tile. Cells hold 125 (refine 1) or
+    16 (refine 2) points, so work items are full (every primary slot of every
+    wavefront) and stencils span many tiles. lmax = 0 integer counts, exact on
+    every precision path."""
+    g = np.arange(40) * 0.5
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    box, edges = 20.0, np.array([0.5, 1.0, 1.5, 2.0, 2.5])
+    ref, _, res = O.run(pos, box, edges, 0, [(0, 0, 0)])
+    for prec in PRECS:
+        got, npairs, _, _ = run_gpu(torch, pos, box, edges, 0, [(0, 0, 0)], prec, refine=refine)
+        assert npairs == res.npairs, PNAME[prec]
+        err = rel_err(got, ref)
+        assert err < 1e-12, (PNAME[prec], err)
+
+
 def test_lattice_ties_on_bin_edges(torch):
     """Dyadic lattice: many pairs exactly on bin edges (half-open bins)."""
     box, edges = 16.0, np.array([0.5, 1.0, 1.5, 2.0, 3.0])
