@@ -522,8 +522,8 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_tmp, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_orig, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pf, sizeof(float4) * N)) != TPCF_OK) return st;
-    // 8 floats of padding: the contraction's staging reads 8-wide windows
-    if ((st = ensure(h, h->d_pw, sizeof(float) * (N + 8))) != TPCF_OK) return st;
+    // 16 floats of padding: the contractions stage 8- and 16-wide windows
+    if ((st = ensure(h, h->d_pw, sizeof(float) * (N + 16))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pa, sizeof(float4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pd, sizeof(double4) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_perm, sizeof(int) * N)) != TPCF_OK) return st;

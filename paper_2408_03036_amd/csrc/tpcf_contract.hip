@@ -320,29 +320,42 @@ __global__ void __launch_bounds__(64 * kIsoWaves) k_contract_iso(ContractArgs a)
     const int nsteps = (int)((pb - p00 + 63) / 64);
     const int nit = nsteps * parts;
     auto group = [&](int it) { return p00 + (int64_t)(it / parts) * 64 + 16 * g; };
-    auto fetch = [&](int it, Raw16<TA>& r0, Raw16<TA>& r1) {
-        const int64_t q0 = group(it);
-        if (q0 < pb) {
-            const int64_t off = (it % parts) * pstep + q0;
-            r0.load(A + row0 + off);
-            if (nt > 1) r1.load(A + row1 + off);
+    // FP32 weights of a group are prefetched with its values (the weight
+    // buffer ends with 16 floats of padding); FP64 reads them from the points
+    constexpr bool F32 = std::is_same<TA, float>::value;
+    constexpr bool WPRE = W && F32;
+    struct Set {
+        Raw16<TA> r0, r1;
+        Raw16<float> w;
+    };
+    // Loads of iteration it into set S: unconditional, a group past the
+    // subchunk reads the first group instead (its values are masked), so the
+    // loads in flight are the same on every path and the wait before a set is
+    // used covers only that set (a two-set ping-pong, no register rotation).
+    auto fetch = [&](int it, Set& S) {
+        int64_t q0 = group(it);
+        if (q0 >= pb) q0 = p00;
+        const int64_t off = (it % parts) * pstep + q0;
+        S.r0.load(A + row0 + off);
+        if (nt > 1) S.r1.load(A + row1 + off);
+        if constexpr (WPRE) {
+            // not 16-byte aligned in general
+            const float* wsrc = a.pw + a.p_begin + q0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) __builtin_memcpy(&S.w.v[q], wsrc + 4 * q, 16);
         }
     };
-    Raw16<TA> c0, c1, n0, n1;
-    if (nit > 0) fetch(0, n0, n1);
     // FP32 operands: FP32 16x16x4 MFMA in two chains, emptied into FP64
     // after every step of 64 primaries (16 products per chain and entry)
-    constexpr bool F32 = std::is_same<TA, float>::value;
     typedef float f32x4 __attribute__((ext_vector_type(4)));
     double accd[3][4];
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) accd[q][r] = 0.0;
-    for (int it = 0; it < nit; ++it) {
-        c0 = n0;
-        c1 = n1;
-        if (it + 1 < nit) fetch(it + 1, n0, n1);
+    auto step = [&](int it, const Set& S) {
+        const Raw16<TA>& c0 = S.r0;
+        const Raw16<TA>& c1 = S.r1;
         const int64_t q0 = group(it);
         const int lo = (int)max<int64_t>(pa - q0, -1), hi = (int)min<int64_t>(pb - q0, 17);
         if constexpr (F32) {
@@ -353,7 +366,7 @@ __global__ void __launch_bounds__(64 * kIsoWaves) k_contract_iso(ContractArgs a)
             for (int k = 0; k < 16; ++k) {
                 const bool in = k >= lo && k < hi;
                 const float x0 = (in && ok0) ? c0.v[k >> 2][k & 3] : 0.0f;
-                const float wk = W ? (in ? (float)a.pw[a.p_begin + q0 + k] : 0.0f) : 1.0f;
+                const float wk = W ? (in ? S.w.v[k >> 2][k & 3] : 0.0f) : 1.0f;
                 const float wa0 = W ? x0 * wk : x0;
                 f32x4* acc = (k & 1) ? sb : sa;
                 acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa0, x0, acc[0], 0, 0, 0);
@@ -382,6 +395,14 @@ __global__ void __launch_bounds__(64 * kIsoWaves) k_contract_iso(ContractArgs a)
                 }
             }
         }
+    };
+    Set sA, sB;
+    if (nit > 0) fetch(0, sA);
+    for (int it = 0; it < nit; it += 2) {
+        fetch(it + 1, sB);
+        step(it, sA);
+        fetch(it + 2, sA);
+        if (it + 1 < nit) step(it + 1, sB);
     }
     // upper triangle of the block: tiles (0,0), (0,1), (1,1)
     const int64_t base = (int64_t)(a.sub_base + s) * a.gsize + a.goff[m];
