@@ -685,8 +685,10 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // loads in flight are the same on every path: the wait before a set
         // is used covers exactly that set, loaded a whole half (K hits of
         // arithmetic) before. (Conditional loads, or rotating registers,
-        // would make every hit wait for the newest load.)
-        constexpr int K = LMAX <= 4 ? 4 : 2;
+        // would make every hit wait for the newest load.) Four records per
+        // set: at lmax = 10 that keeps three waves per SIMD (deeper sets cost
+        // a wave and measured slower).
+        constexpr int K = 4;
         // an empty list reads the first record of the buffer (not accumulated)
         const float4* rec = n > 0 ? a.rec + off : a.rec;
         const uint32_t last = n > 0 ? n - 1 : 0;
