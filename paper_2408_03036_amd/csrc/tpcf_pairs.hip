@@ -554,10 +554,41 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
 
 // ---------------------------------------------------------------- harmonics
 
-template <typename T>
-__device__ constexpr T beta(int l, int m) {
-    return (T)((l + m - 1) * (l - m - 1)) / (T)((2 * l - 1) * (2 * l - 3));
+// Chebyshev coefficients of the z-polynomial parts of the harmonics. The
+// value of order (l, m) carries the monic polynomial q_l^m(z) of degree l - m
+// (q_m = 1, q_{m+1} = z, q_l = z q_{l-1} - beta(l, m) q_{l-2}, the three-term
+// recurrence of the associated Legendre functions divided by their leading
+// coefficient and by (1 - z^2)^(m/2)). Written in Chebyshev polynomials,
+// q_l^m = sum_k d[m][l][k] T_k(z), the coefficients follow from the same
+// recurrence with z T_0 = T_1 and z T_k = (T_{k+1} + T_{k-1}) / 2. They are
+// all non-negative (q_l^m is a Gegenbauer polynomial of index m + 1/2 > 0),
+// so they sum to q_l^m(1) = max |q_l^m| and the change of basis amplifies no
+// rounding error. The m = 0 chain runs to degree 2 lmax (self moments).
+__host__ __device__ constexpr double beta_d(int l, int m) {
+    return (double)((l + m - 1) * (l - m - 1)) / (double)((2 * l - 1) * (2 * l - 3));
 }
+
+template <int LMAX>
+struct ChebTable {
+    static constexpr int N = 2 * LMAX + 1;
+    double d[LMAX + 1][N][N];
+    constexpr ChebTable() : d{} {
+        for (int m = 0; m <= LMAX; ++m) {
+            const int ltop = m == 0 ? 2 * LMAX : LMAX;
+            d[m][m][0] = 1.0;
+            if (m + 1 <= ltop) d[m][m + 1][1] = 1.0;
+            for (int l = m + 2; l <= ltop; ++l) {
+                const double b = beta_d(l, m);
+                for (int k = 0; k < N; ++k) {
+                    double zk = 0.5 * (k + 1 < N ? d[m][l - 1][k + 1] : 0.0);
+                    if (k == 1) zk += d[m][l - 1][0];
+                    if (k >= 2) zk += 0.5 * d[m][l - 1][k - 1];
+                    d[m][l][k] = zk - b * d[m][l - 2][k];
+                }
+            }
+        }
+    }
+};
 
 // Split point of the m range when the values of one bin do not fit one lane.
 __host__ __device__ constexpr int m_split(int lmax) {
@@ -585,34 +616,35 @@ struct Acc {
     T s[NS > 0 ? NS : 1];
 };
 
-// Accumulates one neighbour (unit vector x,y,z; weight w).
-// Accumulates one neighbour (unit vector x,y,z; weight w). With UNIT all
-// weights are 1: the self moments of order L <= lmax then equal the m = 0
-// coefficients and are not accumulated twice (the caller copies them).
+// Accumulates one neighbour (unit vector x,y,z; weight w) in the Chebyshev
+// basis: the slot of order (l, m) sums c_m T_{l-m}(z) with c_m = w (x - i y)^m
+// (and the self moments w^2 T_L(z)); cheb_to_monic turns the sums into the
+// monic polynomial basis once the list is done. The Chebyshev values are
+// shared by every m and cost one fused multiply-add per degree, where the
+// monic recurrence runs once per m. With UNIT all weights are 1: the self
+// moments of order L <= lmax then equal the m = 0 sums and are not
+// accumulated twice (the caller copies them).
 template <typename T, int LMAX, int G, bool UNIT>
 __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) {
     using AC = Acc<T, LMAX, G>;
     constexpr int MLO = AC::MLO, MHI = AC::MHI, V0 = AC::V0;
     constexpr bool SHARE = UNIT && MLO == 0 && AC::SELF;  // s[l] == a[l] for l <= lmax
-    if constexpr (MLO == 0 || AC::SELF) {
-        // m = 0 chain, up to 2 lmax when the self moments are held
-        constexpr int LTOP = AC::SELF ? 2 * LMAX : LMAX;
-        const T w2 = UNIT ? (T)1 : w * w;
-        T r0 = (T)1, r1 = z;
-        if constexpr (MLO == 0) A.a[0 - V0] += UNIT ? (T)1 : w;
-        if constexpr (AC::SELF && !SHARE) A.s[0] += w2;
-        if constexpr (LTOP >= 1) {
-            if constexpr (MLO == 0 && LMAX >= 1) A.a[1 - V0] = UNIT ? A.a[1 - V0] + r1 : fma(w, r1, A.a[1 - V0]);
-            if constexpr (AC::SELF && !(SHARE && 1 <= LMAX)) A.s[1] = UNIT ? A.s[1] + r1 : fma(w2, r1, A.s[1]);
-        }
+    constexpr int KTOP = AC::SELF ? 2 * LMAX : LMAX - MLO;  // highest Chebyshev degree used
+    T t[KTOP + 1];
+    t[0] = (T)1;
+    if constexpr (KTOP >= 1) t[1] = z;
+    const T z2 = z + z;
 #pragma unroll
-        for (int l = 2; l <= LTOP; ++l) {
-            const T r2 = fma(z, r1, -beta<T>(l, 0) * r0);
-            if (MLO == 0 && l <= LMAX) A.a[l - V0] = UNIT ? A.a[l - V0] + r2 : fma(w, r2, A.a[l - V0]);
-            if (AC::SELF && !(SHARE && l <= LMAX)) A.s[l] = UNIT ? A.s[l] + r2 : fma(w2, r2, A.s[l]);
-            r0 = r1;
-            r1 = r2;
-        }
+    for (int k = 2; k <= KTOP; ++k) t[k] = fma(z2, t[k - 1], -t[k - 2]);
+    if constexpr (MLO == 0) {
+#pragma unroll
+        for (int k = 0; k <= LMAX; ++k) A.a[k - V0] = UNIT ? A.a[k - V0] + t[k] : fma(w, t[k], A.a[k - V0]);
+    }
+    if constexpr (AC::SELF) {
+        const T w2 = UNIT ? (T)1 : w * w;
+#pragma unroll
+        for (int k = 0; k <= 2 * LMAX; ++k)
+            if (!(SHARE && k <= LMAX)) A.s[k] = UNIT ? A.s[k] + t[k] : fma(w2, t[k], A.s[k]);
     }
     if constexpr (MHI >= 1) {
         // c_m = w (x - i y)^m
@@ -620,31 +652,49 @@ __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) 
 #pragma unroll
         for (int m = 1; m <= MHI; ++m) {
             if (m > 1) {
-                const T t = fma(cr, x, ci * y);
+                const T u = fma(cr, x, ci * y);
                 ci = fma(ci, x, -(cr * y));
-                cr = t;
+                cr = u;
             }
             if (m >= MLO) {
                 const int vo = value_offset(LMAX, m) - V0;
                 const int nl = LMAX - m + 1;
-                A.a[vo] += cr;
-                A.a[vo + nl] += ci;
-                if (m + 1 <= LMAX) {
-                    T q0 = (T)1, q1 = z;
-                    A.a[vo + 1] = fma(q1, cr, A.a[vo + 1]);
-                    A.a[vo + nl + 1] = fma(q1, ci, A.a[vo + nl + 1]);
 #pragma unroll
-                    for (int l = m + 2; l <= LMAX; ++l) {
-                        const T q2 = fma(z, q1, -beta<T>(l, m) * q0);
-                        A.a[vo + l - m] = fma(q2, cr, A.a[vo + l - m]);
-                        A.a[vo + nl + l - m] = fma(q2, ci, A.a[vo + nl + l - m]);
-                        q0 = q1;
-                        q1 = q2;
-                    }
+                for (int k = 0; k < nl; ++k) {
+                    A.a[vo + k] = fma(t[k], cr, A.a[vo + k]);
+                    A.a[vo + nl + k] = fma(t[k], ci, A.a[vo + nl + k]);
                 }
             }
         }
     }
+}
+
+// In-place change of basis of n consecutive sums of one m from Chebyshev
+// T_0 .. T_{n-1} to q_m^m .. q_{m+n-1}^m: top down, so that every sum still
+// read holds its Chebyshev value (q_{m+j} uses T_j, T_{j-2}, ...).
+template <typename T, int LMAX>
+__device__ __forceinline__ void cheb_run_to_monic(const ChebTable<LMAX>& D, T* v, int m, int n) {
+#pragma unroll
+    for (int j = n - 1; j >= 1; --j) {
+        T s = (T)0;
+#pragma unroll
+        for (int k = j; k >= 0; k -= 2) s = fma((T)D.d[m][m + j][k], v[k], s);
+        v[j] = s;
+    }
+}
+
+template <typename T, int LMAX, int G>
+__device__ __forceinline__ void cheb_to_monic(Acc<T, LMAX, G>& A) {
+    using AC = Acc<T, LMAX, G>;
+    constexpr ChebTable<LMAX> D{};
+#pragma unroll
+    for (int m = AC::MLO; m <= AC::MHI; ++m) {
+        const int vo = value_offset(LMAX, m) - AC::V0;
+        const int nl = LMAX - m + 1;
+        cheb_run_to_monic<T, LMAX>(D, A.a + vo, m, nl);
+        if (m >= 1) cheb_run_to_monic<T, LMAX>(D, A.a + vo + nl, m, nl);
+    }
+    if constexpr (AC::SELF) cheb_run_to_monic<T, LMAX>(D, A.s, 0, 2 * LMAX + 1);
 }
 
 template <typename T, int LMAX, int G, bool UNIT>
@@ -686,9 +736,10 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // is used covers exactly that set, loaded a whole half (K hits of
         // arithmetic) before. (Conditional loads, or rotating registers,
         // would make every hit wait for the newest load.) Four records per
-        // set: at lmax = 10 that keeps three waves per SIMD (deeper sets cost
-        // a wave and measured slower).
-        constexpr int K = 4;
+        // set, eight where the sums alone take more than 128 registers: such
+        // a lane runs at two waves per SIMD whatever the depth, and the
+        // deeper sets hide more of the load latency there.
+        constexpr int K = AC::NA + AC::NS > 128 ? 8 : 4;
         // an empty list reads the first record of the buffer (not accumulated)
         const float4* rec = n > 0 ? a.rec + off : a.rec;
         const uint32_t last = n > 0 ? n - 1 : 0;
@@ -770,6 +821,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l - AC::V0];
     }
+    cheb_to_monic(acc);
     T* A = reinterpret_cast<T*>(a.A);
     const int64_t ld = a.ldA;
 #pragma unroll
@@ -846,6 +898,7 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
         for (int i = 0; i < AC::NS; ++i)
             for (int o = 32; o > 0; o >>= 1) acc.s[i] += __shfl_xor(acc.s[i], o, 64);
     }
+    cheb_to_monic(acc);
     // lane i writes value i
     float* A = reinterpret_cast<float*>(a.A);
     const int64_t ld = a.ldA;
