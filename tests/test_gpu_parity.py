@@ -153,6 +153,31 @@ def test_weighted_data_minus_randoms(torch, prec):
     assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("lmax", [8, 12])
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32, T.PREC_MIXED_BF16X6])
+def test_high_lmax_split_harmonics(torch, prec, lmax, weighted):
+    """High orders, where the harmonic pass splits the m range of a list over
+    two launches (FP64 from lmax 7 on, FP32 from lmax 11 on), with unit
+    weights (the self moments of order <= lmax shared with the m = 0 sums) and
+    with data-minus-randoms weights. The FP32 pass is the one of every mixed
+    path; the 3-product split is left to the dense configuration, since its
+    degenerate-triangle error grows with 2l+1 over the few neighbours per bin
+    of this catalogue."""
+    box, edges = 60.0, np.array([2.0, 5.0, 8.0, 12.0])
+    nd, nr = 300, 600
+    pos = np.vstack([C.zeldovich(nd, box, 1.5, 0.8, 93, grid=16), C.randoms(nr, box, 94)])
+    w = C.dr_weights(nd, nr) if weighted else None
+    n_data = nd if weighted else None
+    mults = O.all_multipoles(lmax, 2)
+    ref, _, res = O.run(pos, box, edges, lmax, mults, w=w, n_data=n_data)
+    got, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec, w=w, n_data=n_data)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  lmax {lmax} weighted={weighted} {PNAME[prec]} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_single_cell_box_and_bins_from_zero(torch, prec):
     """rmax close to L/2: one cell with per-pair minimum image; first bin from 0."""
