@@ -675,13 +675,19 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
 
 // Degenerate-triangle moments sum_p w_p sum_j w_j^2 R^0_L(z_pj) and pair
 // counts per bin. One workgroup per (subchunk, group of kSelfTasks tasks); the
-// subchunk's primary weights are staged in LDS once, and every wavefront sums
-// its tasks with four independent FP64 partial sums in a fixed order.
+// subchunk's primary weights are staged in LDS once (not with unit weights),
+// and every wavefront sums its tasks with four independent FP64 partial sums
+// in a fixed order. A row is streamed kSelfUnroll loads per lane at a time, so
+// that enough loads are in flight to cover the memory latency. With unit
+// weights the pair count of a bin is its L = 0 moment (an exact integer sum),
+// written by that task.
 constexpr int kSelfTasks = 16;
 constexpr int kSelfMaxSub = 4096;  // primaries per subchunk
+constexpr int kSelfUnroll = 16;
 
+template <bool UNIT>
 __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
-    __shared__ double wsh[kSelfMaxSub];
+    __shared__ double wsh[UNIT ? 1 : kSelfMaxSub];
     const int s = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nL = 2 * a.lmax + 1;
@@ -691,26 +697,34 @@ __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
     const int na = n_alm_values(a.lmax);
     const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
     const int n = (int)(pb - pa);
-    for (int i = threadIdx.x; i < n; i += 256) wsh[i] = a.pd[a.p_begin + pa + i].w;
-    __syncthreads();
+    if constexpr (!UNIT) {
+        for (int i = threadIdx.x; i < n; i += 256) wsh[i] = a.pd[a.p_begin + pa + i].w;
+        __syncthreads();
+    }
+    const int nfull = n / (64 * kSelfUnroll) * (64 * kSelfUnroll);
     for (int q = 0; q < kSelfTasks / 4; ++q) {
         const int task = blockIdx.y * kSelfTasks + wave * (kSelfTasks / 4) + q;
         if (task >= ntask) break;
         const int b = task / width, L = task - b * width;
+        if (UNIT && L == nL) continue;  // written by the L = 0 task
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (L < nL) {
             const int64_t row = ((int64_t)b * NV + na + L) * a.ldA + pa;
-            for (int p0 = 0; p0 < n; p0 += 256) {
+            auto val = [&](int p) {
+                return a.fp64 ? reinterpret_cast<const double*>(a.A)[row + p]
+                              : (double)reinterpret_cast<const float*>(a.A)[row + p];
+            };
+            for (int p0 = 0; p0 < nfull; p0 += 64 * kSelfUnroll) {
+                double v[kSelfUnroll];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kSelfUnroll; ++u) v[u] = val(p0 + 64 * u + lane);
+#pragma unroll
+                for (int u = 0; u < kSelfUnroll; ++u) {
                     const int p = p0 + 64 * u + lane;
-                    if (p < n) {
-                        const double v = a.fp64 ? reinterpret_cast<const double*>(a.A)[row + p]
-                                                : (double)reinterpret_cast<const float*>(a.A)[row + p];
-                        acc[u] += wsh[p] * v;
-                    }
+                    acc[u & 3] += UNIT ? v[u] : wsh[p] * v[u];
                 }
             }
+            for (int p = nfull + lane; p < n; p += 64) acc[0] += UNIT ? val(p) : wsh[p] * val(p);
         } else {
             for (int p0 = 0; p0 < n; p0 += 256) {
 #pragma unroll
@@ -722,7 +736,11 @@ __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
         }
         double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-        if (lane == 0) a.part[(int64_t)(a.sub_base + s) * a.nb * width + task] = sum;
+        if (lane == 0) {
+            double* out = a.part + (int64_t)(a.sub_base + s) * a.nb * width;
+            out[task] = sum;
+            if (UNIT && L == 0) out[b * width + nL] = sum;
+        }
     }
 }
 
@@ -991,8 +1009,11 @@ size_t contract_lds_bytes(int mode, int nb, int lmax) {
 hipError_t launch_self_moments(const SelfArgs& a, hipStream_t s) {
     if (a.nsub <= 0) return hipSuccess;
     const int ntask = a.nb * (2 * a.lmax + 2);
-    hipLaunchKernelGGL(k_self_moments, dim3(a.nsub, (ntask + kSelfTasks - 1) / kSelfTasks), dim3(256), 0, s,
-                       a);
+    const dim3 grid(a.nsub, (ntask + kSelfTasks - 1) / kSelfTasks);
+    if (a.unit_w)
+        hipLaunchKernelGGL(k_self_moments<true>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_self_moments<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -223,6 +223,7 @@ struct SelfArgs {
     int sub_base;
     double* part;            // [nsub_total][nb*(2lmax+2)]: moments then pair count per bin
     int fp64;
+    int unit_w;              // all weights 1 (pd[].w not read)
 };
 hipError_t launch_self_moments(const SelfArgs& a, hipStream_t s);
 
