@@ -80,6 +80,8 @@ struct tpcf_handle_s {
     std::vector<int64_t> pt_off;
     std::vector<double> n_data;
     bool unit_w = true;
+    bool self_lo = false;  // tpcf_run_catalogs with multipoles of L <= lmax only (no per-m export)
+    bool self_cut = false;  // the summed self moments stop at order lmax (set by such a run)
     DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
         d_catid, d_flag, d_istart, d_icell, d_icat, d_scanw;
     std::vector<int> item_cat;       // [ncat+1] first work item of each catalogue
@@ -758,6 +760,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     // a wavefront per list once lists average 256 records or more (the
     // predicted hits of a primary of the densest catalogue, over the bins)
     a.wave_per_list = (!h->fp64 && h->lmax <= 6 && h->hits_per_list >= 256.0) ? 1 : 0;
+    a.self_lo = h->self_lo ? 1 : 0;
     a.boff = P<uint32_t>(h->d_boff);
     a.cnt = P<uint32_t>(h->d_cnt);
     a.A = h->d_A.p;
@@ -859,8 +862,14 @@ tpcf_status finalize_group(tpcf_handle h, int32_t n_mult, const int32_t* mult, d
         for (int m = 0; m <= std::min(l1, l2); ++m) {
             const double base = 8.0 * kPi * kPi * (2.0 * L + 1.0) * qv(h, l1, l2, m, L) * (m > 0 ? 2.0 : 1.0) * f;
             cg[t * s1 + m] = base * h->scale[l1 * s1 + m] * h->scale[l2 * s1 + m];
-            for (int L2 = 0; L2 < nL; ++L2)
-                cs[((size_t)t * s1 + m) * nL + L2] = base * 0.5 * (2.0 * L2 + 1.0) * qv(h, l1, l2, m, L2) * h->gamma0[L2];
+            // Degenerate triangles: the product of the two harmonics at one
+            // point expands into self moments of every order L2, but summed
+            // over m (with the 3j weights of this multipole) the coefficient
+            // of each order L2 != L vanishes (orthogonality of the 3j symbols
+            // (l1 l2 L; m -m 0) over m). Only the order-L term is kept, so the
+            // result needs no self moment above L and carries no rounding
+            // residue of the cancelling orders.
+            cs[((size_t)t * s1 + m) * nL + L] = base * 0.5 * (2.0 * L + 1.0) * qv(h, l1, l2, m, L) * h->gamma0[L];
         }
     }
     tpcf_status st;
@@ -1006,6 +1015,7 @@ tpcf_status tpcf_build_grid(tpcf_handle h, const double* d_pos, const double* d_
     HIPCHK(hipSetDevice(h->device));
     h->stage = 0;
     h->pairs_valid = false;
+    h->self_cut = false;
     tpcf_status st = build_grid_group(h, d_pos, d_w, {n}, {n_data});
     if (st != TPCF_OK) return st;
     h->stage = 1;
@@ -1064,6 +1074,8 @@ tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out) {
         h->stage = 3;
     }
     if (d_nnn_out) {
+        if (h->self_cut)
+            return fail(h, TPCF_ERR_STATE, "tpcf_run_catalogs keeps no per-m sums; use the step calls");
         NnnArgs a{};
         a.G = P<double>(h->d_G);
         a.goff = P<int64_t>(h->d_goff);
@@ -1086,6 +1098,10 @@ tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2
     if (st != TPCF_OK) return st;
     if (!d_out) return fail(h, TPCF_ERR_ARG, "d_out is NULL");
     if (h->stage < 3) return fail(h, TPCF_ERR_STATE, "tpcf_contract must come first");
+    if (h->self_cut)
+        for (int t = 0; t < n_mult; ++t)
+            if (h_l1l2L[3 * t + 2] > h->lmax)
+                return fail(h, TPCF_ERR_STATE, "the self moments of the last tpcf_run_catalogs stop at order lmax");
     HIPCHK(hipSetDevice(h->device));
     return finalize_group(h, n_mult, h_l1l2L, d_out);
 }
@@ -1098,6 +1114,8 @@ tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n, c
         return fail(h, TPCF_ERR_ARG, "ncat >= 1 and non-NULL h_n, h_n_data, d_pos, d_out required");
     tpcf_status st = check_mults(h, n_mult, h_l1l2L);
     if (st != TPCF_OK) return st;
+    int max_L = 0;
+    for (int t = 0; t < n_mult; ++t) max_L = std::max(max_L, (int)h_l1l2L[3 * t + 2]);
     for (int c = 0; c < ncat; ++c) {
         if (h_n[c] < 1 || h_n[c] > (1LL << 27)) return fail(h, TPCF_ERR_ARG, "catalogue size out of range");
         if (h_n_data[c] < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
@@ -1119,7 +1137,14 @@ tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n, c
             return st;
         if ((st = check_nonfinite(h)) != TPCF_OK) return st;
         if ((st = plan_chunks(h)) != TPCF_OK) return st;
-        if ((st = pair_pass(h, true)) != TPCF_OK) return st;
+        // The self moments of order above lmax cancel from every multipole
+        // of L <= lmax (their coefficients sum to zero over m), and this run
+        // keeps no per-m sums: the harmonic pass may stop them at lmax.
+        h->self_lo = max_L <= h->lmax;
+        h->self_cut = h->self_lo;
+        st = pair_pass(h, true);
+        h->self_lo = false;
+        if (st != TPCF_OK) return st;
         if ((st = reduce_group(h)) != TPCF_OK) return st;
         h->stage = 3;
         if ((st = finalize_group(h, n_mult, h_l1l2L, d_out + per_out * c0)) != TPCF_OK) return st;

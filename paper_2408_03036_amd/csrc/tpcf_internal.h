@@ -127,6 +127,7 @@ struct AlmArgs {
     const float4* rec;       // hit records (dx, dy, dz, w_j) (FP32 paths)
     int unit_w;              // all weights are 1
     int wave_per_list;       // long lists: one wavefront per (p, b) list (FP32, lmax <= 6)
+    int self_lo;             // FP32 whole-m lanes: self moments only to order lmax (run asks for L <= lmax)
     const uint32_t* boff;
     const uint32_t* cnt;
     void* A;                 // [nb][nvalues][ldA] float or double

@@ -616,6 +616,15 @@ struct Acc {
     T s[NS > 0 ? NS : 1];
 };
 
+// Highest order of the self moments a lane accumulates: 2 lmax, or lmax with
+// SLO. The self moments enter the multipoles only through the removal of the
+// degenerate triangles, and there the coefficient of the order-L' moment,
+// summed over m, vanishes for every L' other than the multipole's own L (the
+// orthogonality of the 3j symbols (l1 l2 L; m -m 0) over m). A run whose
+// multipoles all have L <= lmax, and that exports no per-m sums, needs none
+// of the orders above lmax.
+__host__ __device__ constexpr int self_top(int lmax, bool slo) { return slo ? lmax : 2 * lmax; }
+
 // Accumulates one neighbour (unit vector x,y,z; weight w) in the Chebyshev
 // basis: the slot of order (l, m) sums c_m T_{l-m}(z) with c_m = w (x - i y)^m
 // (and the self moments w^2 T_L(z)); cheb_to_monic turns the sums into the
@@ -623,13 +632,15 @@ struct Acc {
 // shared by every m and cost one fused multiply-add per degree, where the
 // monic recurrence runs once per m. With UNIT all weights are 1: the self
 // moments of order L <= lmax then equal the m = 0 sums and are not
-// accumulated twice (the caller copies them).
-template <typename T, int LMAX, int G, bool UNIT>
+// accumulated twice (the caller copies them). With SLO the self moments stop
+// at order lmax (those above are left 0; see self_top).
+template <typename T, int LMAX, int G, bool UNIT, bool SLO = false>
 __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) {
     using AC = Acc<T, LMAX, G>;
     constexpr int MLO = AC::MLO, MHI = AC::MHI, V0 = AC::V0;
     constexpr bool SHARE = UNIT && MLO == 0 && AC::SELF;  // s[l] == a[l] for l <= lmax
-    constexpr int KTOP = AC::SELF ? 2 * LMAX : LMAX - MLO;  // highest Chebyshev degree used
+    constexpr int STOP = self_top(LMAX, SLO);
+    constexpr int KTOP = AC::SELF ? (STOP > LMAX - MLO ? STOP : LMAX - MLO) : LMAX - MLO;  // highest Chebyshev degree used
     T t[KTOP + 1];
     t[0] = (T)1;
     if constexpr (KTOP >= 1) t[1] = z;
@@ -643,7 +654,7 @@ __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) 
     if constexpr (AC::SELF) {
         const T w2 = UNIT ? (T)1 : w * w;
 #pragma unroll
-        for (int k = 0; k <= 2 * LMAX; ++k)
+        for (int k = 0; k <= STOP; ++k)
             if (!(SHARE && k <= LMAX)) A.s[k] = UNIT ? A.s[k] + t[k] : fma(w2, t[k], A.s[k]);
     }
     if constexpr (MHI >= 1) {
@@ -683,7 +694,7 @@ __device__ __forceinline__ void cheb_run_to_monic(const ChebTable<LMAX>& D, T* v
     }
 }
 
-template <typename T, int LMAX, int G>
+template <typename T, int LMAX, int G, bool SLO = false>
 __device__ __forceinline__ void cheb_to_monic(Acc<T, LMAX, G>& A) {
     using AC = Acc<T, LMAX, G>;
     constexpr ChebTable<LMAX> D{};
@@ -694,10 +705,10 @@ __device__ __forceinline__ void cheb_to_monic(Acc<T, LMAX, G>& A) {
         cheb_run_to_monic<T, LMAX>(D, A.a + vo, m, nl);
         if (m >= 1) cheb_run_to_monic<T, LMAX>(D, A.a + vo + nl, m, nl);
     }
-    if constexpr (AC::SELF) cheb_run_to_monic<T, LMAX>(D, A.s, 0, 2 * LMAX + 1);
+    if constexpr (AC::SELF) cheb_run_to_monic<T, LMAX>(D, A.s, 0, self_top(LMAX, SLO) + 1);
 }
 
-template <typename T, int LMAX, int G, bool UNIT>
+template <typename T, int LMAX, int G, bool UNIT, bool SLO>
 __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
     using AC = Acc<T, LMAX, G>;
     constexpr int NV = n_values(LMAX);
@@ -737,8 +748,10 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // arithmetic) before. (Conditional loads, or rotating registers,
         // would make every hit wait for the newest load.) Four records per
         // set, eight where the sums alone take more than 128 registers: such
-        // a lane runs at two waves per SIMD whatever the depth, and the
-        // deeper sets hide more of the load latency there.
+        // a lane runs at two waves per SIMD, and a set of eight records is a
+        // whole 128-byte line of its list (with four, the two halves of a
+        // line are fetched a set apart, and were measured slower even at
+        // three waves).
         constexpr int K = AC::NA + AC::NS > 128 ? 8 : 4;
         // an empty list reads the first record of the buffer (not accumulated)
         const float4* rec = n > 0 ? a.rec + off : a.rec;
@@ -749,7 +762,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         auto hit = [&](const float4 q) {
             const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
             const float inv = __builtin_amdgcn_rsqf(d2);
-            add_hit<T, LMAX, G, UNIT>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+            add_hit<T, LMAX, G, UNIT, SLO>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
         };
         for (uint32_t t = 0; t < n; t += 2 * K) {
 #pragma unroll
@@ -789,7 +802,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
             double inv = __builtin_amdgcn_rsq(r2);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
             inv = inv * fma(-0.5 * r2 * inv, inv, 1.5);
-            add_hit<T, LMAX, G, UNIT>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d.w);
+            add_hit<T, LMAX, G, UNIT, SLO>(acc, (T)(dx * inv), (T)(dy * inv), (T)(dz * inv), (T)d.w);
         };
         uint32_t ea[K], eb[K];
         double4 da[K], db[K];
@@ -821,7 +834,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l - AC::V0];
     }
-    cheb_to_monic(acc);
+    cheb_to_monic<T, LMAX, G, SLO>(acc);
     T* A = reinterpret_cast<T*>(a.A);
     const int64_t ld = a.ldA;
 #pragma unroll
@@ -842,7 +855,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
 // the lane-per-list loads, and their partial sums would cost occupancy).
 constexpr int kWaveListWaves = 4;
 
-template <int LMAX, bool UNIT>
+template <int LMAX, bool UNIT, bool SLO>
 __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a) {
     using AC = Acc<float, LMAX, 0>;
     constexpr int NV = n_values(LMAX);
@@ -869,7 +882,7 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
     auto hit = [&](const float4 q) {
         const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
         const float inv = __builtin_amdgcn_rsqf(d2);
-        add_hit<float, LMAX, 0, UNIT>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+        add_hit<float, LMAX, 0, UNIT, SLO>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
     };
     for (uint32_t t0 = 0; t0 < n; t0 += 128 * K) {
 #pragma unroll
@@ -891,14 +904,14 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l];
 #pragma unroll
-        for (int i = LMAX + 1; i < AC::NS; ++i)
+        for (int i = LMAX + 1; i <= self_top(LMAX, SLO); ++i)
             for (int o = 32; o > 0; o >>= 1) acc.s[i] += __shfl_xor(acc.s[i], o, 64);
     } else {
 #pragma unroll
-        for (int i = 0; i < AC::NS; ++i)
+        for (int i = 0; i <= self_top(LMAX, SLO); ++i)
             for (int o = 32; o > 0; o >>= 1) acc.s[i] += __shfl_xor(acc.s[i], o, 64);
     }
-    cheb_to_monic(acc);
+    cheb_to_monic<float, LMAX, 0, SLO>(acc);
     // lane i writes value i
     float* A = reinterpret_cast<float*>(a.A);
     const int64_t ld = a.ldA;
@@ -917,20 +930,33 @@ hipError_t launch_alm_one(const AlmArgs& a, hipStream_t s) {
         if (a.wave_per_list) {
             const int64_t nw = (nprim * a.nb + kWaveListWaves - 1) / kWaveListWaves;
             const int64_t nwg = (nw + 7) / 8 * 8;
-            if (a.unit_w)
-                hipLaunchKernelGGL((k_pair_alm_wave<LMAX, true>), dim3((unsigned)nwg), dim3(64 * kWaveListWaves), 0, s, a);
-            else
-                hipLaunchKernelGGL((k_pair_alm_wave<LMAX, false>), dim3((unsigned)nwg), dim3(64 * kWaveListWaves), 0, s, a);
+            const dim3 grid((unsigned)nwg), block(64 * kWaveListWaves);
+            if (a.unit_w) {
+                if (a.self_lo) hipLaunchKernelGGL((k_pair_alm_wave<LMAX, true, true>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_pair_alm_wave<LMAX, true, false>), grid, block, 0, s, a);
+            } else {
+                if (a.self_lo) hipLaunchKernelGGL((k_pair_alm_wave<LMAX, false, true>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_pair_alm_wave<LMAX, false, false>), grid, block, 0, s, a);
+            }
             return hipGetLastError();
         }
     }
     const int64_t nwaves = ((nprim + 255) / 256) * a.nb * 4;
     const int64_t nwg = (nwaves + 7) / 8 * 8;
-    // unit weights: the FP32 single-launch kernel shares the m = 0 sums
-    if (sizeof(T) == 4 && G == 0 && a.unit_w)
-        hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, true>), dim3((unsigned)nwg), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, false>), dim3((unsigned)nwg), dim3(64), 0, s, a);
+    const dim3 grid((unsigned)nwg), block(64);
+    if constexpr (sizeof(T) == 4 && G == 0) {
+        // unit weights: the FP32 single-launch kernel shares the m = 0 sums;
+        // self_lo: the self moments stop at order lmax
+        if (a.unit_w) {
+            if (a.self_lo) hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, true, false>), grid, block, 0, s, a);
+        } else {
+            if (a.self_lo) hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, false, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, false, false>), grid, block, 0, s, a);
+        }
+    } else {
+        hipLaunchKernelGGL((k_pair_alm<T, LMAX, G, false, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

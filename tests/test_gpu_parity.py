@@ -300,6 +300,44 @@ def test_crowded_cluster_exact_rebinning(torch, prec):
     assert rel_err(out.cpu().numpy(), ref) < TOL[prec]
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("prec", [T.PREC_FP32, T.PREC_MIXED_BF16X3])
+def test_run_catalogs_self_orders(torch, prec, weighted):
+    """A batched run whose multipoles all have L <= lmax stops the self
+    moments at order lmax (the others cancel from every such multipole). Its
+    result equals that of the step calls, which keep every order, bit for bit;
+    afterwards the per-m export and multipoles of L > lmax are refused."""
+    box, edges, lmax, n = 150.0, np.linspace(10.0, 40.0, 4), 4, 3000
+    cats = [C.zeldovich(n, box, 3.0, 0.8, 151 + i, grid=32) for i in range(2)]
+    ws = [np.random.default_rng(161 + i).uniform(0.5, 1.5, n) for i in range(2)] if weighted else [None, None]
+    mults = O.all_multipoles(lmax, 2)
+    h = T.Handle(box, edges, lmax, precision=prec)
+    out = h.run_catalogs([n, n], [n, n], gpu(torch, np.vstack(cats)),
+                         gpu(torch, np.concatenate(ws)) if weighted else None, mults)
+    h.sync()
+    batched = out.cpu().numpy()
+    with pytest.raises(T.TpcfError) as e:
+        h.contract(export=True)
+    assert e.value.status == T.TPCF_ERR_STATE
+    with pytest.raises(T.TpcfError) as e:
+        h.multipoles([(4, 4, 6)])
+    assert e.value.status == T.TPCF_ERR_STATE
+    h.close()
+    for i in range(2):
+        h = T.Handle(box, edges, lmax, precision=prec)
+        h.build_grid(gpu(torch, cats[i]), gpu(torch, ws[i]))
+        h.alm_accumulate()
+        h.contract()
+        single = h.multipoles(mults).cpu().numpy()
+        h.sync()
+        h.close()
+        assert np.array_equal(single, batched[i]), i
+    ref, _, _ = O.run(cats[0], box, edges, lmax, mults, w=ws[0])
+    err = rel_err(batched[0], ref)
+    say(f"  batched self orders {PNAME[prec]} weighted={weighted} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
 def test_nonfinite_positions_reported(torch):
     pos = C.poisson(500, 50.0, 141)
     pos[17, 1] = np.nan
