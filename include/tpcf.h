@@ -173,6 +173,12 @@ tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2
  * and uses h_n_data[c] in its RRR. Results go to d_out, ncat x n_mult x nbins
  * x nbins float64. Catalogues are processed in groups that fit the workspace
  * limit; results do not depend on the grouping.
+ * When every requested L is <= lmax, the self moments of order above lmax are
+ * not accumulated (they cancel from such multipoles, the 3j symbols of a
+ * multipole being orthogonal over m); the results equal those of steps 1-4 bit
+ * for bit. Until the next tpcf_build_grid the handle then refuses, with
+ * TPCF_ERR_STATE, a tpcf_contract export of NNN^m and tpcf_multipoles triples
+ * with L > lmax.
  */
 tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n,
                               const int64_t* h_n_data, const double* d_pos, const double* d_w,
