@@ -648,8 +648,9 @@ __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) 
 #pragma unroll
     for (int k = 2; k <= KTOP; ++k) t[k] = fma(z2, t[k - 1], -t[k - 2]);
     if constexpr (MLO == 0) {
+        // with UNIT the degree-0 sum is the number of neighbours, set by the caller
 #pragma unroll
-        for (int k = 0; k <= LMAX; ++k) A.a[k - V0] = UNIT ? A.a[k - V0] + t[k] : fma(w, t[k], A.a[k - V0]);
+        for (int k = UNIT ? 1 : 0; k <= LMAX; ++k) A.a[k - V0] = UNIT ? A.a[k - V0] + t[k] : fma(w, t[k], A.a[k - V0]);
     }
     if constexpr (AC::SELF) {
         const T w2 = UNIT ? (T)1 : w * w;
@@ -830,6 +831,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         }
     }
     if (!active) return;
+    if constexpr (UNIT && AC::MLO == 0) acc.a[0 - AC::V0] = (T)n;  // exact: lists hold < 2^24 hits
     if constexpr (UNIT && AC::MLO == 0 && AC::SELF) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l - AC::V0];
@@ -900,6 +902,7 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
 #pragma unroll
     for (int i = 0; i < AC::NA; ++i)
         for (int o = 32; o > 0; o >>= 1) acc.a[i] += __shfl_xor(acc.a[i], o, 64);
+    if constexpr (UNIT) acc.a[0] = (float)n;  // the degree-0 sum: the list length
     if constexpr (UNIT) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l];
