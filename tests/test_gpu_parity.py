@@ -507,3 +507,10 @@ def test_long_lists_wave_kernel(torch, weighted):
     err = rel_err(outs[T.PREC_FP32], outs[T.PREC_FP64])
     say(f"  long lists FP32 vs FP64 rel err {err:.2e}")
     assert err < 1e-5
+    # the batched call runs the same kernel with the self moments stopped at
+    # lmax (every L here is <= lmax): bit for bit the step calls' result
+    h = T.Handle(box, edges, lmax, precision=T.PREC_FP32)
+    batched = h.run_catalogs([n], [n], gpu(torch, pos), gpu(torch, w), mults).cpu().numpy()
+    h.sync()
+    h.close()
+    assert np.array_equal(batched[0], outs[T.PREC_FP32])
