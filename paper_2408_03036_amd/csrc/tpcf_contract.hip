@@ -244,6 +244,168 @@ __global__ void __launch_bounds__(256) k_contract(ContractArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- FP64, double-buffered
+// The FP64 contraction of k_contract<0> (16x16 tiles, eight per wavefront,
+// 16x16x4 FP64 MFMA, the same LDS layout) with the staging of the
+// split-BF16 kernel. Per step (KS primaries of one part) every thread owns up
+// to kF64IPT items of four consecutive primaries of one column. Their loads
+// for step st + 1 (two 16-byte loads per item, unconditional and in bounds:
+// the operand buffer ends with 8 elements of padding, and an idle item or one
+// past the step's primaries reads the start of the buffer or of its row) are
+// issued before the MFMAs of step st and stored into the other LDS buffer
+// after them, with the elements that are not the step's primaries zeroed.
+// Used when the items of the widest m fit the workgroup and two buffers fit
+// LDS; k_contract<0> covers the other shapes.
+constexpr int kF64IPT = 4;
+
+__host__ __device__ constexpr size_t f64db_lds(int ncol) {
+    return 2 * (size_t)(Cfg<0>::KS + ncol * (Cfg<0>::KS + 1)) * sizeof(double);
+}
+
+template <bool W>
+__global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
+    using C = Cfg<0>;
+    constexpr int TS = C::TS, KS = C::KS, TPW = C::TPW, KSP = KS + 1;
+    extern __shared__ unsigned char smem[];
+    const int s = blockIdx.x;
+    const int m = blockIdx.y;
+    const int lmax = a.lmax, nb = a.nb;
+    const int nl = lmax - m + 1;
+    const int K = nb * nl;
+    const int nt = (K + TS - 1) / TS;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int t0 = blockIdx.z * 4 * TPW;
+    if (t0 >= ntiles) return;
+    const int parts = m == 0 ? 1 : 2;
+    const int NV = n_values(lmax);
+    const int voff = value_offset(lmax, m);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
+    const int ncol = nt * TS;
+
+    int ti[TPW], tj[TPW];
+    bool tv[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int t = t0 + wave + 4 * q;
+        tv[q] = t < ntiles;
+        tile_of(tv[q] ? t : 0, nt, ti[q], tj[q]);
+    }
+    f64x4 acc64[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc64[q] = (f64x4)0.0;
+
+    // per buffer: KS weights, then X[col][k] with stride KSP
+    const int bufd = KS + ncol * KSP;
+    double* lds = reinterpret_cast<double*>(smem);
+    const double* A = reinterpret_cast<const double*>(a.A);
+    constexpr int groups = KS / 4;
+    const int nitems = ncol * groups;
+    const int nkst = (int)((pb - pa + KS - 1) / KS);
+    const int nsteps = nkst * parts;
+
+    // the thread's items: column c, primaries k4 .. k4+3 of the step
+    int64_t irow[kF64IPT];
+    int ioff[kF64IPT], ik4[kF64IPT];
+    bool iok[kF64IPT], istore[kF64IPT];
+#pragma unroll
+    for (int u = 0; u < kF64IPT; ++u) {
+        const int it = threadIdx.x + u * 256;
+        const int c = it / groups, k4 = (it - c * groups) * 4;
+        const int b = c / nl, lp = c - b * nl;
+        istore[u] = it < nitems;
+        iok[u] = it < nitems && c < K;
+        ik4[u] = k4;
+        ioff[u] = c * KSP + k4;
+        irow[u] = ((int64_t)b * NV + voff + lp) * a.ldA;
+    }
+    const int64_t part_stride = (int64_t)nl * a.ldA;
+
+    struct Stage {
+        double x[kF64IPT][4];
+        double w;
+    };
+    auto load = [&](int st, Stage& R) {
+        const int part = st % parts;
+        const int64_t p0 = pa + (int64_t)(st / parts) * KS;
+        const int kv = (int)min((int64_t)KS, pb - p0);
+#pragma unroll
+        for (int u = 0; u < kF64IPT; ++u) {
+            const int kk = ik4[u] < kv ? ik4[u] : 0;
+            const double* src = A + (iok[u] ? irow[u] + part * part_stride + p0 + kk : 0);
+            double2 v0, v1;
+            __builtin_memcpy(&v0, src, 16);
+            __builtin_memcpy(&v1, src + 2, 16);
+            R.x[u][0] = v0.x;
+            R.x[u][1] = v0.y;
+            R.x[u][2] = v1.x;
+            R.x[u][3] = v1.y;
+        }
+        if constexpr (W) {
+            // thread k (< KS) stages the weight of primary k of the step
+            const int k = threadIdx.x % KS;
+            R.w = a.pd[a.p_begin + p0 + (k < kv ? k : 0)].w;
+        }
+    };
+    auto store = [&](int st, int buf, const Stage& R) {
+        double* base = lds + buf * bufd;
+        const int64_t p0 = pa + (int64_t)(st / parts) * KS;
+        const int kv = (int)min((int64_t)KS, pb - p0);
+        if constexpr (W) {
+            if (threadIdx.x < KS) base[threadIdx.x] = (int)threadIdx.x < kv ? R.w : 0.0;
+        }
+        double* X = base + KS;
+#pragma unroll
+        for (int u = 0; u < kF64IPT; ++u) {
+            if (!istore[u]) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = iok[u] && ik4[u] + e < kv;
+                X[ioff[u] + e] = ok ? R.x[u][e] : 0.0;
+            }
+        }
+    };
+    const int i = lane & 15, kg = lane >> 4;
+    auto compute = [&](int buf) {
+        const double* base = lds + buf * bufd;
+        const double* X = base + KS;
+        for (int k0 = 0; k0 < KS; k0 += 4) {
+            const double wv = W ? base[k0 + kg] : 1.0;
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                if (!tv[q]) continue;
+                const double av = X[(ti[q] * TS + i) * KSP + k0 + kg] * wv;
+                const double bv = X[(tj[q] * TS + i) * KSP + k0 + kg];
+                acc64[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[q], 0, 0, 0);
+            }
+        }
+    };
+
+    Stage R;
+    load(0, R);
+    store(0, 0, R);
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        if (st + 1 < nsteps) load(st + 1, R);
+        compute(st & 1);
+        if (st + 1 < nsteps) store(st + 1, (st + 1) & 1, R);
+        __syncthreads();
+    }
+    const int64_t sg = (int64_t)(a.sub_base + s);
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        if (!tv[q]) continue;
+        const int j = lane & 15;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = (lane >> 4) + 4 * r;
+            const int ci = ti[q] * TS + ii, cj = tj[q] * TS + j;
+            if (ci < K && cj < K) a.part64[sg * a.gsize + a.goff[m] + (int64_t)ci * K + cj] = acc64[q][r];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- isotropic schedule
 // The isotropic multipoles are the L = 0 case of eq. (slep2sugy) (Sec. 2.3:
 // the tripolar basis with L = 0 reduces to Legendre polynomials of the angle
@@ -914,6 +1076,27 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
     const int nt0 = (K0 + C::TS - 1) / C::TS;
     const int ntiles0 = nt0 * (nt0 + 1) / 2;
     const int ngroups = (ntiles0 + 4 * C::TPW - 1) / (4 * C::TPW);
+    if constexpr (MODE == 0) {
+        // the double-buffered kernel when its items and buffers fit
+        const int ncol = nt0 * C::TS;
+        const size_t lds2 = f64db_lds(ncol);
+        if (ncol * (C::KS / 4) <= 256 * kF64IPT && lds2 <= 160 * 1024) {
+            static bool attr2 = false;
+            if (!attr2) {
+                hipFuncSetAttribute((const void*)k_contract_f64<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024);
+                hipFuncSetAttribute((const void*)k_contract_f64<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024);
+                attr2 = true;
+            }
+            const dim3 grid(a.nsub, a.lmax + 1, ngroups);
+            if (a.unit_weights)
+                hipLaunchKernelGGL(k_contract_f64<false>, grid, dim3(256), lds2, s, a);
+            else
+                hipLaunchKernelGGL(k_contract_f64<true>, grid, dim3(256), lds2, s, a);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = contract_lds<MODE>(nt0 * C::TS);
     static bool attr = false;
     if (!attr) {
