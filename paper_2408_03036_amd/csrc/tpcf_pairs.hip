@@ -783,8 +783,12 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // two stages: a set's entries are loaded one half before its points
         // are gathered, and the points one half before they are accumulated.
         // A slot past the end of the list gathers the primary itself (not
-        // accumulated), so every address is valid.
-        constexpr int K = 2;
+        // accumulated), so every address is valid. The gathers are
+        // latency-bound: the kernels that split the m range (lmax >= 7, two
+        // waves per SIMD or one) keep six entries and points per set in
+        // flight (lmax 10: 360 ms per step with two, 320 with three, 287 with
+        // four, 274 with six or eight).
+        constexpr int K = G == 0 ? 2 : 6;
         const int64_t pself = active ? p : a.p_begin;
         const int64_t cstart = a.pt_off[a.catid[pself]];
         const double4 P64 = a.pd[pself];
