@@ -686,6 +686,10 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
         b.p_end = ch.p_end;
         b.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
         b.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
+        // unit weights with the whole m range in one FP32 lane (lmax <= 10):
+        // the harmonic kernels that read the records (their UNIT forms) take
+        // no weight, so a record is (dx, dy, dz)
+        b.rec3 = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
         b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
         b.cursor = P<unsigned long long>(h->d_lcursor);
         b.capacity = h->list_cap;

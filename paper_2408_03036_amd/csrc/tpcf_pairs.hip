@@ -204,7 +204,11 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
         const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
         if (SWEEP == 2 && pos >= c.capoff[b + 1]) return;
         if constexpr (REC) {
-            a.rec[base_g + pos] = make_float4(dx, dy, dz, w);
+            if (a.rec3)
+                *reinterpret_cast<float3*>(reinterpret_cast<float*>(a.rec) + 3 * (size_t)(base_g + pos)) =
+                    make_float3(dx, dy, dz);
+            else
+                a.rec[base_g + pos] = make_float4(dx, dy, dz, w);
         } else {
             a.list[base_g + pos] = entry;
         }
@@ -755,11 +759,22 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // three waves).
         constexpr int K = AC::NA + AC::NS > 128 ? 8 : 4;
         // an empty list reads the first record of the buffer (not accumulated)
-        const float4* rec = n > 0 ? a.rec + off : a.rec;
+        const size_t roff = n > 0 ? off : 0;
         const uint32_t last = n > 0 ? n - 1 : 0;
+        // with UNIT the records are 12 bytes (dx, dy, dz)
+        const float4* rec = a.rec + roff;
+        const float3* rec3 = reinterpret_cast<const float3*>(reinterpret_cast<const float*>(a.rec) + 3 * roff);
+        auto load_rec = [&](uint32_t i) {
+            if constexpr (UNIT) {
+                const float3 v = rec3[i];
+                return make_float4(v.x, v.y, v.z, 1.f);
+            } else {
+                return rec[i];
+            }
+        };
         float4 qa[K], qb[K];
 #pragma unroll
-        for (int i = 0; i < K; ++i) qa[i] = rec[min((uint32_t)i, last)];
+        for (int i = 0; i < K; ++i) qa[i] = load_rec(min((uint32_t)i, last));
         auto hit = [&](const float4 q) {
             const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
             const float inv = __builtin_amdgcn_rsqf(d2);
@@ -767,12 +782,12 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         };
         for (uint32_t t = 0; t < n; t += 2 * K) {
 #pragma unroll
-            for (int i = 0; i < K; ++i) qb[i] = rec[min(t + K + i, last)];
+            for (int i = 0; i < K; ++i) qb[i] = load_rec(min(t + K + i, last));
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 if (t + i < n) hit(qa[i]);
 #pragma unroll
-            for (int i = 0; i < K; ++i) qa[i] = rec[min(t + 2 * K + i, last)];
+            for (int i = 0; i < K; ++i) qa[i] = load_rec(min(t + 2 * K + i, last));
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 if (t + K + i < n) hit(qb[i]);
@@ -880,11 +895,22 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
     // the same ping-pong of unconditional loads as the lane-per-list kernel,
     // over blocks of 64 consecutive records (n is uniform over the wavefront)
     constexpr int K = 2;
-    const float4* rec = n > 0 ? a.rec + a.boff[pl * a.nb + b] : a.rec;
+    const size_t roff = n > 0 ? a.boff[pl * a.nb + b] : 0;
     const uint32_t last = n > 0 ? n - 1 : 0;
+    // with UNIT the records are 12 bytes (dx, dy, dz)
+    const float4* rec = a.rec + roff;
+    const float3* rec3 = reinterpret_cast<const float3*>(reinterpret_cast<const float*>(a.rec) + 3 * roff);
+    auto load_rec = [&](uint32_t i) {
+        if constexpr (UNIT) {
+            const float3 v = rec3[i];
+            return make_float4(v.x, v.y, v.z, 1.f);
+        } else {
+            return rec[i];
+        }
+    };
     float4 qa[K], qb[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i) qa[i] = rec[min((uint32_t)(64 * i + lane), last)];
+    for (int i = 0; i < K; ++i) qa[i] = load_rec(min((uint32_t)(64 * i + lane), last));
     auto hit = [&](const float4 q) {
         const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
         const float inv = __builtin_amdgcn_rsqf(d2);
@@ -892,12 +918,12 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
     };
     for (uint32_t t0 = 0; t0 < n; t0 += 128 * K) {
 #pragma unroll
-        for (int i = 0; i < K; ++i) qb[i] = rec[min(t0 + 64 * (K + i) + lane, last)];
+        for (int i = 0; i < K; ++i) qb[i] = load_rec(min(t0 + 64 * (K + i) + lane, last));
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if (t0 + 64 * i + lane < n) hit(qa[i]);
 #pragma unroll
-        for (int i = 0; i < K; ++i) qa[i] = rec[min(t0 + 64 * (2 * K + i) + lane, last)];
+        for (int i = 0; i < K; ++i) qa[i] = load_rec(min(t0 + 64 * (2 * K + i) + lane, last));
 #pragma unroll
         for (int i = 0; i < K; ++i)
             if (t0 + 64 * (K + i) + lane < n) hit(qb[i]);
