@@ -97,8 +97,9 @@ def time_steps(torch, h, sizes, pos, mults, steps, warmup):
 def measured_traffic(kernel_sources):
     """HBM bytes per launch of the dominant kernel, from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes summarised in profiles/ (scaled by the copy-kernel
-    calibration recorded there). None once the kernel's sources differ from the
-    ones the counters were taken on."""
+    calibration recorded there). None once the kernel's sources, or the host
+    code that sizes its launches, differ from the ones the counters were taken
+    on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_pair_alm_batched64_lmax10_traffic.json")
     try:
@@ -440,7 +441,8 @@ def main():
     traffic = None
     if args.ncat == 64 and prec_id != T.PREC_FP64:
         traffic = measured_traffic(["paper_2408_03036_amd/csrc/tpcf_pairs.hip",
-                                    "paper_2408_03036_amd/csrc/tpcf_internal.h"])
+                                    "paper_2408_03036_amd/csrc/tpcf_internal.h",
+                                    "paper_2408_03036_amd/csrc/tpcf.cpp"])
     roof = {"kernel": "k_pair_alm<float,10> (harmonic pass)", "bound": "alu",
             "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU, "traffic": traffic,

@@ -563,7 +563,12 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
 }
 
 // Bytes per hit in the neighbour lists.
-size_t list_elem_bytes(tpcf_handle h) { return h->fp64 ? sizeof(uint32_t) : sizeof(float4); }
+// Bytes per hit: 4-byte list entries (FP64 path), 16-byte records (FP32), or
+// 12-byte records with unit weights at lmax <= 10 (as the binning writes them).
+size_t list_elem_bytes(tpcf_handle h) {
+    if (h->fp64) return sizeof(uint32_t);
+    return (h->unit_w && h->lmax <= 10) ? 3 * sizeof(float) : sizeof(float4);
+}
 
 // Splits every catalogue into subchunks of kc primaries and groups whole
 // subchunks into chunks whose a_lm operand and hit lists fit the workspace share.
@@ -578,7 +583,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     int64_t maxn = 0;
     for (int c = 0; c < h->ncat; ++c) maxn = std::max(maxn, h->pt_off[c + 1] - h->pt_off[c]);
     const double hits = std::min((double)maxn, maxn / L3 * shell);
-    // hit lists: 4-byte entries (FP64 path) or 16-byte records (FP32 paths);
+    // hit lists: 4-byte entries (FP64 path) or 12/16-byte records (FP32 paths);
     // room for the predicted bin regions of a primary of the densest
     // catalogue (the binning kernel's margin), plus the rare exact rebins (a
     // list that overflows is rebuilt with twice the room)
@@ -592,7 +597,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     h->hits_per_list = hits / h->nb;
     int64_t budget = h->limit / 2;
     int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
-    cap = std::min<int64_t>(cap, 1 << 20);
+    cap = std::min<int64_t>(cap, 1 << 21);
     // list offsets are 32-bit: keep a chunk's predicted room within 3.5e9 entries
     cap = std::min<int64_t>(cap, (int64_t)(3.5e9 / hits_room));
     cap = std::max<int64_t>(h->kc, cap / h->kc * h->kc);
