@@ -1081,14 +1081,9 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
         const int ncol = nt0 * C::TS;
         const size_t lds2 = f64db_lds(ncol);
         if (ncol * (C::KS / 4) <= 256 * kF64IPT && lds2 <= 160 * 1024) {
-            static bool attr2 = false;
-            if (!attr2) {
-                hipFuncSetAttribute((const void*)k_contract_f64<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    160 * 1024);
-                hipFuncSetAttribute((const void*)k_contract_f64<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    160 * 1024);
-                attr2 = true;
-            }
+            const hipError_t e = a.unit_weights ? allow_full_lds((const void*)k_contract_f64<false>)
+                                                : allow_full_lds((const void*)k_contract_f64<true>);
+            if (e != hipSuccess) return e;
             const dim3 grid(a.nsub, a.lmax + 1, ngroups);
             if (a.unit_weights)
                 hipLaunchKernelGGL(k_contract_f64<false>, grid, dim3(256), lds2, s, a);
@@ -1098,12 +1093,8 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
         }
     }
     const size_t lds = contract_lds<MODE>(nt0 * C::TS);
-    static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute((const void*)k_contract<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-        attr = true;
-    }
+    const hipError_t e = allow_full_lds((const void*)k_contract<MODE>);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_contract<MODE>, dim3(a.nsub, a.lmax + 1, ngroups), dim3(256), lds, s, a);
     return hipGetLastError();
 }
@@ -1134,12 +1125,8 @@ hipError_t launch_contract_bf16_w(const ContractArgs& a, hipStream_t s) {
     const int ngroups = (ntiles0 + kBfWaves * kBfTPW - 1) / (kBfWaves * kBfTPW);
     const BfPlan pl = bf_plan(NPC, nt0 * 32, !a.unit_weights);
     if (pl.KS == 0) return hipErrorInvalidValue;
-    static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute((const void*)k_contract_bf16<NPC, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-        attr = true;
-    }
+    const hipError_t e = allow_full_lds((const void*)k_contract_bf16<NPC, W>);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_contract_bf16<NPC, W>), dim3(a.nsub, a.lmax + 1, ngroups), dim3(64 * kBfWaves),
                        pl.lds, s, a, pl.KS, pl.nbuf);
     return hipGetLastError();
@@ -1223,8 +1210,7 @@ hipError_t launch_edge_iso(const double* N, const double* R, const double* T, in
     const int kThreads = (int)std::max<size_t>(1, std::min<size_t>(32, (size_t)160 * 1024 / per));
     const size_t lds = (size_t)kThreads * per;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_edge_iso, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
+        hipError_t e = allow_full_lds((const void*)k_edge_iso);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_edge_iso, dim3((nbb + kThreads - 1) / kThreads), dim3(kThreads), lds, s, N, R, T, nl, nbb,

@@ -139,6 +139,13 @@ struct AlmArgs {
 };
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s);
 
+// Lets a kernel take up to a CU's 160 KiB of LDS. The limit belongs to the
+// device current at the call, so launchers set it before every launch (a
+// host-side call of a few microseconds) rather than once per process.
+inline hipError_t allow_full_lds(const void* kernel) {
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
 // 2PCF pair counts (tpcf_xi.hip)
 constexpr int kXiMaxBins = 16384;  // nb * nmu: one uint32 LDS counter per (r, mu) bin
 struct XiArgs {

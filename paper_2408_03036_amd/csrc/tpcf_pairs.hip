@@ -1020,12 +1020,8 @@ hipError_t launch_alm_lmax(const AlmArgs& a, int fp64, hipStream_t s) {
 
 template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
 hipError_t launch_bin_variant(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
-    static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute((const void*)k_pair_bin<SINGLE, UNIFORM, REC, FIX>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr = true;
-    }
+    const hipError_t e = allow_full_lds((const void*)k_pair_bin<SINGLE, UNIFORM, REC, FIX>);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_pair_bin<SINGLE, UNIFORM, REC, FIX>), dim3((unsigned)nblk), dim3(64 * kNW), lds, s, a);
     return hipGetLastError();
 }

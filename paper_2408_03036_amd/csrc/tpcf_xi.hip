@@ -367,8 +367,7 @@ template <bool SINGLE, bool UNIFORM>
 hipError_t launch_xi_variant(const XiArgs& a, hipStream_t s) {
     const size_t lds = xi_lds_bytes(a.nb, a.nmu, a.npmax);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_xi_count<SINGLE, UNIFORM>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = allow_full_lds((const void*)k_xi_count<SINGLE, UNIFORM>);
         if (e != hipSuccess) return e;
     }
     int dev = 0, ncu = 0, per_cu = 0;
