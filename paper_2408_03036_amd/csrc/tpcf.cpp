@@ -827,6 +827,7 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     s.part = P<double>(h->d_pself);
     s.fp64 = h->fp64;
     s.unit_w = h->unit_w ? 1 : 0;
+    s.self_lo = h->self_lo ? 1 : 0;
     HIPCHK(launch_self_moments(s, h->stream));
     t_end(h, t);
     return TPCF_OK;

@@ -870,7 +870,9 @@ __global__ void __launch_bounds__(256) k_self_moments(SelfArgs a) {
         const int b = task / width, L = task - b * width;
         if (UNIT && L == nL) continue;  // written by the L = 0 task
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (L < nL) {
+        if (a.self_lo && L > a.lmax && L < nL) {
+            // not written by the harmonic pass of such a run: the moment is zero
+        } else if (L < nL) {
             const int64_t row = ((int64_t)b * NV + na + L) * a.ldA + pa;
             auto val = [&](int p) {
                 return a.fp64 ? reinterpret_cast<const double*>(a.A)[row + p]

@@ -233,6 +233,7 @@ struct SelfArgs {
     double* part;            // [nsub_total][nb*(2lmax+2)]: moments then pair count per bin
     int fp64;
     int unit_w;              // all weights 1 (pd[].w not read)
+    int self_lo;             // orders above lmax neither written by the harmonic pass nor read: zero
 };
 hipError_t launch_self_moments(const SelfArgs& a, hipStream_t s);
 

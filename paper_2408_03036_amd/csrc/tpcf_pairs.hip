@@ -861,8 +861,10 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
 #pragma unroll
     for (int i = 0; i < AC::NA; ++i) A[((int64_t)b * NV + AC::V0 + i) * ld + pl] = acc.a[i];
     if constexpr (AC::SELF) {
+        // with SLO the orders above lmax are zero and not stored (the
+        // self-moment sums of such a run do not read them)
 #pragma unroll
-        for (int i = 0; i < AC::NS; ++i)
+        for (int i = 0; i <= self_top(LMAX, SLO); ++i)
             A[((int64_t)b * NV + n_alm_values(LMAX) + i) * ld + pl] = acc.s[i];
     }
 }
