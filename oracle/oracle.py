@@ -14,18 +14,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpcf_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_DEFAULT = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+# ORACLE_LIBRARY selects another build (for example the sanitized one)
+_LIB = os.environ.get("ORACLE_LIBRARY") or _LIB_DEFAULT
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, OpenMP, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP, no FMA contraction). With
+    sanitize, an AddressSanitizer + UndefinedBehaviorSanitizer build
+    (liboracle_san.so), to be loaded with gcc's libasan preloaded."""
+    out = _LIB_SAN if sanitize else _LIB_DEFAULT
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        san = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer"] if sanitize else []
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-                               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-ffp-contract=off", "-fno-fast-math"] + san + [_SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Params(ctypes.Structure):
@@ -39,7 +47,8 @@ class _Params(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        build()
+        if _LIB == _LIB_DEFAULT:
+            build()
         _lib = ctypes.CDLL(_LIB)
         _lib.oracle_estimate.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]
@@ -225,3 +234,118 @@ def edge_correct_isotropic(N, R):
                     M[l, lp] = sum(w3[l, lp, lpp] * R[lpp, b1, b2] for lpp in range(nl))
             out[:, b1, b2] = np.linalg.solve(M, N[:, b1, b2])
     return out
+
+
+# ------------------------------------------------------------------ edge correction (anisotropic)
+
+
+def gaunt_conj(l, m, lp, mp, lpp, mpp):
+    """Integral over the sphere of conj(Y_lm) Y_l'm' Y_l''m'' (orthonormal,
+    Condon-Shortley phase), from the 3j symbols: conj(Y_lm) = (-1)^m Y_l,-m and
+    the integral of three harmonics is
+    sqrt((2l1+1)(2l2+1)(2l3+1)/(4 pi)) (l1 l2 l3; 0 0 0) (l1 l2 l3; m1 m2 m3)."""
+    if m != mp + mpp or abs(m) > l or abs(mp) > lp or abs(mpp) > lpp:
+        return 0.0
+    if lpp < abs(l - lp) or lpp > l + lp or (l + lp + lpp) % 2:
+        return 0.0
+    f = np.sqrt((2 * l + 1) * (2 * lp + 1) * (2 * lpp + 1) / (4.0 * np.pi))
+    sign = -1.0 if m % 2 else 1.0
+    return sign * f * wigner3j(l, lp, lpp, 0, 0, 0) * wigner3j(l, lp, lpp, -m, mp, mpp)
+
+
+def edge_correct_anisotropic(N, R):
+    """Edge-corrected anisotropic 3PCF coefficients from the data-minus-randoms
+    triplet counts N and the random triplet counts R (Szapudi-Szalay estimator,
+    eq. (ssest): zeta = (D - R)^3 / R^3 as functions of the triangle).
+
+    N and R are complex arrays [m][l1][l2][b1][b2], m = 0..lmax, of the
+    coefficients of real functions of the two sides' directions in the basis
+    Y_{l1 m}(r1) conj(Y_{l2 m}(r2)) (the coefficients of m < 0 are the
+    conjugates), normalised alike (for example NNN^m / RRR of each run). The
+    relation N(r1, r2) = zeta(r1, r2) R(r1, r2) at every pair of directions
+    reads, coefficient by coefficient,
+        N^m_{l1 l2} = sum zeta^{m'}_{l1' l2'} R^{m-m'}_{l1'' l2''}
+                      G(l1 m; l1' m'; l1'' m-m') G(l2 m; l2' m'; l2'' m-m'),
+    G(l m; l' m'; l'' m'') = integral of conj(Y_lm) Y_l'm' Y_l''m''; every
+    index is truncated at lmax. The system is solved for zeta at each
+    (b1, b2); zeta is returned in the layout of N (complex, m >= 0)."""
+    N = np.asarray(N, dtype=np.complex128)
+    R = np.asarray(R, dtype=np.complex128)
+    s1 = N.shape[0]
+    nb1, nb2 = N.shape[3], N.shape[4]
+    idx = [(l1, l2, m) for l1 in range(s1) for l2 in range(s1)
+           for m in range(-min(l1, l2), min(l1, l2) + 1)]
+    n = len(idx)
+    # coupling entries (row, column, l1'', l2'', m'', weight), independent of (b1, b2)
+    I, J, C1, C2, MM, W = [], [], [], [], [], []
+    for i, (l1, l2, m) in enumerate(idx):
+        for j, (a1, a2, mp) in enumerate(idx):
+            mpp = m - mp
+            for c1 in range(abs(mpp), s1):
+                g1 = gaunt_conj(l1, m, a1, mp, c1, mpp)
+                if g1 == 0.0:
+                    continue
+                for c2 in range(abs(mpp), s1):
+                    g2 = gaunt_conj(l2, m, a2, mp, c2, mpp)
+                    if g2 == 0.0:
+                        continue
+                    I.append(i)
+                    J.append(j)
+                    C1.append(c1)
+                    C2.append(c2)
+                    MM.append(mpp)
+                    W.append(g1 * g2)
+    I, J, C1, C2, MM, W = (np.array(v) for v in (I, J, C1, C2, MM, W))
+    am = np.abs(MM)
+
+    def value(X, l1, l2, m, b1, b2):
+        v = X[np.abs(m), l1, l2, b1, b2]
+        return np.where(m < 0, np.conj(v), v)
+
+    rl1 = np.array([t[0] for t in idx])
+    rl2 = np.array([t[1] for t in idx])
+    rm = np.array([t[2] for t in idx])
+    out = np.zeros_like(N)
+    for b1 in range(nb1):
+        for b2 in range(nb2):
+            rv = R[am, C1, C2, b1, b2]
+            rv = np.where(MM < 0, np.conj(rv), rv)
+            M = np.zeros((n, n), dtype=np.complex128)
+            np.add.at(M, (I, J), W * rv)
+            rhs = value(N, rl1, rl2, rm, b1, b2)
+            z = np.linalg.solve(M, rhs)
+            for k, (l1, l2, m) in enumerate(idx):
+                if m >= 0:
+                    out[m, l1, l2, b1, b2] = z[k]
+    return out
+
+
+def multipoles_from_coefficients(Z, lmax, mults, literal=False):
+    """TripoSH coefficients c_{l1 l2 L}(b1, b2) of the function whose
+    orthonormal-basis coefficients are Z (complex [m][l1][l2][b1][b2], m >= 0,
+    already normalised): the formula of oracle_multipoles without the
+    division by RRR. Returns (re, im) [n_mult][b1][b2]."""
+    Z = np.asarray(Z, dtype=np.complex128)
+    nb1, nb2 = Z.shape[3], Z.shape[4]
+    re = np.zeros((len(mults), nb1, nb2))
+    im = np.zeros((len(mults), nb1, nb2))
+    for t, (l1, l2, L) in enumerate(mults):
+        H = wigner3j(l1, l2, L, 0, 0, 0)
+        pref = ((2 * L + 1) * H * 16.0 * np.pi ** 2 if literal
+                else 4.0 * np.pi * np.sqrt((2 * l1 + 1) * (2 * l2 + 1)) * (2 * L + 1) * H)
+        s = np.zeros((nb1, nb2), dtype=np.complex128)
+        for m in range(-min(l1, l2), min(l1, l2) + 1):
+            v = Z[abs(m), l1, l2]
+            v = np.conj(v) if m < 0 else v
+            s += wigner3j(l1, l2, L, m, -m, 0) * (-1.0 if m % 2 else 1.0) * v
+        re[t] = pref * s.real
+        im[t] = pref * s.imag
+    return re, im
+
+
+def rrr(n_data, box, edges):
+    """Analytic random-triplet count RRR(b1, b2) = N (N-1)(N-2) V_b1 V_b2 / L^6 (periodic box)."""
+    e = np.asarray(edges, dtype=np.float64)
+    V = 4.0 * np.pi / 3.0 * (e[1:] ** 3 - e[:-1] ** 3)
+    nd = float(n_data)
+    return nd * (nd - 1.0) * (nd - 2.0) * np.outer(V, V) / box ** 6
