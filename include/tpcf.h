@@ -273,6 +273,28 @@ tpcf_status tpcf_covariance(tpcf_handle h, int32_t n_mocks, int64_t stride, cons
                             const int64_t* h_offsets, double* d_mean, double* d_cov);
 
 /*
+ * tpcf_covariance without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same kernels and same results, bit for bit, as
+ * tpcf_covariance on the same inputs; it calls no hipMalloc or hipFree.
+ *  d_offsets: DEVICE array of n_d int64 offsets into a row, or NULL (the first
+ *             n_d entries). The host cannot check device offsets: an offset
+ *             outside 0 .. stride-1 reads nothing and gives NaN in its row and
+ *             column of d_cov (and in d_mean).
+ *  Other arguments as for tpcf_covariance.
+ * The gathered data vectors and the partial products live in a static device
+ * array of 32 MiB (32 << 20 bytes) that every device the library runs on holds
+ * until the process ends: 8 (n_mocks n_d + P) bytes must fit it, P being the
+ * partial products (n_mocks = 3000, n_d = 336 needs 24.3 MB). Larger inputs are
+ * refused with TPCF_ERR_RANGE before any device work. Every call on one device
+ * uses that device's one array: calls that overlap on one device (on two
+ * streams, or from two handles) race and give wrong results; calls in one
+ * stream's order do not. Nothing in the array needs to start at zero.
+ */
+tpcf_status tpcf_covariance_noalloc(tpcf_handle h, int32_t n_mocks, int64_t stride, const double* d_src, int32_t n_d,
+                                    const int64_t* d_offsets, double* d_mean, double* d_cov);
+
+/*
  * Precision matrix with the Hartlap correction (eq. (Hartlap)):
  *   d_prec = (N_m - N_d - 2)/(N_m - 1) * inverse(d_cov),
  * by a Gauss-Jordan sweep in FP64 (d_prec may equal d_cov: in place).

@@ -115,6 +115,8 @@ struct tpcf_handle_s {
     DevBuf d_covx, d_covoff, d_covflag, d_covpart;
     // edge correction
     DevBuf d_edgeT;
+    // device address of the static scratch of the allocation-free covariance
+    void* cov_scratch = nullptr;
 
     // timing
     bool timing = false;
@@ -981,6 +983,12 @@ tpcf_status tpcf_create(const tpcf_config* cfg, int device, void* hip_stream, tp
     h->fp64 = cfg->precision == TPCF_PREC_FP64 ? 1 : 0;
     h->refine = cfg->grid_refine;
     h->limit = cfg->workspace_limit > 0 ? cfg->workspace_limit : (64LL << 30);
+    // the device's address of the allocation-free covariance's scratch (looked
+    // up once per device, with the device current)
+    if (cov_scratch_init(device, &h->cov_scratch) != hipSuccess) {
+        tpcf_destroy(h);
+        return TPCF_ERR_DEVICE;
+    }
     st = setup_constants(h);
     if (st != TPCF_OK) {
         tpcf_destroy(h);
@@ -1344,6 +1352,25 @@ tpcf_status tpcf_covariance(tpcf_handle h, int32_t n_mocks, int64_t stride, cons
     }
     HIPCHK(launch_cov(d_src, stride, doff, n_mocks, n_d, P<double>(h->d_covx), P<double>(h->d_covpart), d_mean, d_cov,
                       h->stream));
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_covariance_noalloc(tpcf_handle h, int32_t n_mocks, int64_t stride, const double* d_src, int32_t n_d,
+                                    const int64_t* d_offsets, double* d_mean, double* d_cov) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_src || !d_cov) return fail(h, TPCF_ERR_ARG, "NULL source or covariance");
+    if (n_mocks < 2) return fail(h, TPCF_ERR_ARG, "n_mocks must be >= 2");
+    if (n_d < 1 || stride < 1) return fail(h, TPCF_ERR_ARG, "n_d and stride must be >= 1");
+    if (!d_offsets && n_d > stride) return fail(h, TPCF_ERR_ARG, "n_d > stride without offsets");
+    const int64_t need = cov_scratch_need(n_mocks, n_d);
+    if (need > kCovScratchBytes)
+        return fail(h, TPCF_ERR_RANGE, "n_mocks x n_d needs " + std::to_string(need) + " bytes of scratch, over the " +
+                                           std::to_string(kCovScratchBytes) + " of the allocation-free covariance");
+    if (!h->cov_scratch) return fail(h, TPCF_ERR_STATE, "no scratch address for this device");
+    HIPCHK(hipSetDevice(h->device));
+    double* X = static_cast<double*>(h->cov_scratch);
+    double* part = X + (int64_t)n_mocks * n_d;
+    HIPCHK(launch_cov(d_src, stride, d_offsets, n_mocks, n_d, X, part, d_mean, d_cov, h->stream));
     return TPCF_OK;
 }
 

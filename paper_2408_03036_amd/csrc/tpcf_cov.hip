@@ -15,6 +15,7 @@
 //                 pivoting), ping-pong between two buffers; k_cov_scale
 //                 applies the Hartlap factor. A non-positive pivot sets a flag.
 #include <algorithm>
+#include <mutex>
 
 #include "tpcf_internal.h"
 
@@ -24,12 +25,15 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// An offset outside a row (possible only for offsets given in device memory,
+// which the host cannot check) reads nothing and gives NaN.
 __global__ void k_cov_gather(const double* __restrict__ src, int64_t stride, const int64_t* __restrict__ off,
                              int nm, int nd, double* __restrict__ X) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)nm * nd) return;
     const int k = (int)(t / nd), i = (int)(t % nd);
-    X[t] = src[(int64_t)k * stride + (off ? off[i] : (int64_t)i)];
+    const int64_t o = off ? off[i] : (int64_t)i;
+    X[t] = (o >= 0 && o < stride) ? src[(int64_t)k * stride + o] : __builtin_nan("");
 }
 
 // Column sums over chunks of kMeanChunk mocks (one thread per (chunk, entry)),
@@ -138,6 +142,39 @@ __global__ void k_cov_scale(const double* __restrict__ A, double* __restrict__ B
 }
 
 }  // namespace
+
+// Scratch of the allocation-free covariance (tpcf_covariance_noalloc): the
+// gathered data vectors and the partial products, kCovScratchBytes on every
+// device the library runs on, held until the process ends. Host code never
+// passes the array's name to a kernel or a copy: it is a host-side stand-in
+// there. It uses the device address that cov_scratch_init looks up once per
+// device.
+__device__ __align__(256) static unsigned char scratch[kCovScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t cov_scratch_init(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        // the caller has made `device` current
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+int64_t cov_scratch_need(int nm, int nd) {
+    return (int64_t)sizeof(double) * ((int64_t)nm * nd + cov_part_doubles(nm, nd));
+}
 
 int64_t cov_part_doubles(int nm, int nd) {
     const int64_t prod = (int64_t)cov_slices(nm, nd) * nd * nd;

@@ -193,6 +193,13 @@ int cov_slices(int nm, int nd);
 int64_t cov_part_doubles(int nm, int nd);  // size of `part`: the slices' products and the mean's sums
 hipError_t launch_cov(const double* src, int64_t stride, const int64_t* off, int nm, int nd, double* X,
                       double* part, double* mean, double* C, hipStream_t s);
+// Allocation-free covariance: a static device array of kCovScratchBytes per
+// device. cov_scratch_init (with `device` current) returns its device address,
+// looked up once per device; cov_scratch_need gives the bytes launch_cov uses
+// for X followed by `part`.
+constexpr int64_t kCovScratchBytes = 32ll << 20;
+hipError_t cov_scratch_init(int device, void** out);
+int64_t cov_scratch_need(int nm, int nd);
 // A (n x n, symmetric positive definite) <- scale * A^-1 in place, W (n x n) as workspace;
 // *bad |= 1 on a non-positive pivot.
 hipError_t launch_cov_invert(double* A, double* W, int n, double scale, int* bad, hipStream_t s);

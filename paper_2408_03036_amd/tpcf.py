@@ -36,7 +36,7 @@ EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
            "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles", "tpcf_triangle_index",
-           "tpcf_covariance", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic",
+           "tpcf_covariance", "tpcf_covariance_noalloc", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic",
            "tpcf_autotune"]
 
 
@@ -102,6 +102,8 @@ def load():
     lib.tpcf_triangle_index.restype = st
     lib.tpcf_covariance.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
     lib.tpcf_covariance.restype = st
+    lib.tpcf_covariance_noalloc.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
+    lib.tpcf_covariance_noalloc.restype = st
     lib.tpcf_precision_matrix.argtypes = [vp, i32, vp, i32, vp]
     lib.tpcf_precision_matrix.restype = st
     lib.tpcf_percival_m1.argtypes = [i32, i32, i32, ctypes.POINTER(dbl)]
@@ -292,6 +294,25 @@ class Handle:
                                            None if off is None else ctypes.c_void_p(off.ctypes.data),
                                            _ptr(mean), _ptr(cov)))
         self._keep_off = off
+        return mean, cov
+
+    def covariance_noalloc(self, src, n_d=None, offsets=None, mean=None, cov=None):
+        """covariance() through the allocation-free entry point: offsets (int64)
+        and the outputs are device tensors given by the caller (allocated here
+        only when not given)."""
+        import torch
+        _check_dev(src, torch.float64, "src")
+        _check_dev(offsets, torch.int64, "offsets")
+        nm, stride = src.shape
+        nd = int(offsets.shape[0]) if offsets is not None else int(stride if n_d is None else n_d)
+        if mean is None:
+            mean = torch.empty(nd, dtype=torch.float64, device=src.device)
+        if cov is None:
+            cov = torch.empty((nd, nd), dtype=torch.float64, device=src.device)
+        _check_dev(mean, torch.float64, "mean")
+        _check_dev(cov, torch.float64, "cov")
+        self._chk(self.lib.tpcf_covariance_noalloc(self.h, nm, stride, _ptr(src), nd, _ptr(offsets),
+                                                   _ptr(mean), _ptr(cov)))
         return mean, cov
 
     def precision(self, cov, n_mocks, out=None):
