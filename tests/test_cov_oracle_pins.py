@@ -79,6 +79,30 @@ def test_percival_limits():
     assert abs((V.percival_m1(nm, 200, 5) - 1.0) * nm - (200 - 2 * 5 - 1)) < 0.1
 
 
+def _golden_percival():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "percival_m1.json")) as f:
+        return json.load(f)["values"]
+
+
+@pytest.mark.parametrize("g", _golden_percival(), ids=lambda g: f"Nm{g['n_mocks']}_Nd{g['n_d']}_Np{g['n_params']}")
+def test_percival_golden_fractions(g):
+    """m1 and the Hartlap factor against exact fractions evaluated by hand from
+    eqs. (Perc1), (Perc) and (Hartlap) (tests/golden/percival_m1.json). At
+    N_m = 298 a changed constant in A (2 -> 3) moves m1 by 3e-5 and a changed
+    "-2" in B by 4e-3 relative, far above the 4-ulp tolerance."""
+    from fractions import Fraction
+    nm, nd, npar = g["n_mocks"], g["n_d"], g["n_params"]
+    m1 = Fraction(*g["m1"])
+    assert abs(V.percival_m1(nm, nd, npar) - float(m1)) <= 4 * np.spacing(float(m1))
+    hl = Fraction(*g["hartlap"])
+    assert abs(V.hartlap_factor(nm, nd) - float(hl)) <= 2 * np.spacing(float(hl))
+    # the fractions are consistent with each other (A, B -> m1)
+    a, b = Fraction(*g["A"]), Fraction(*g["B"])
+    assert (1 + b * (nd - npar)) / (1 + a + b * (npar + 1)) == m1
+
+
 @pytest.mark.parametrize("nb,eta", [(12, 1), (12, 3), (12, 11), (5, 2)])
 def test_triangle_counts_closed_form(nb, eta):
     """Without r_min, the pairs b1 < b2 with b2 - b1 >= eta number (nb - eta)(nb - eta + 1) / 2."""

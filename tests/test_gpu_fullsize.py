@@ -1,15 +1,18 @@
 """Parity at full workload sizes, through the C ABI, in the configurations
 the benchmark runs.
 
-The oracle cannot form the multipoles of a 10^5-point catalogue in test time,
-so at these sizes it checks what it can compute primary by primary: a_lm(p, b)
-of a slice of primaries (Sec. 4.2, eq. (alm)) needs only those primaries'
-neighbours. The batched run of 64 catalogues is checked by properties that hold
-at any size: each catalogue of the batch equals the same catalogue run alone,
-bit for bit; the mixed path agrees with the FP64 path within the split-BF16
-tolerance; and one catalogue's a_lm slice matches the oracle. A data + 5x
-randoms catalogue with data-minus-randoms weights checks every precision
-against the FP64 path at full size.
+The multipoles of whole catalogues are compared element by element with the
+oracle (Sec. 4.2, eqs. (alm), (measured_mult), (slep2sugy)): two catalogues
+of the benchmark's 64-catalogue batch taken from the batched runs (split-BF16
+and FP64), a 10^5-point catalogue on the FP32 and FP64 paths, and a
+4x10^5-point catalogue with L <= 4 on the split-BF16 and FP64 paths (the
+oracle needs 5 to 60 s of 16 host threads for each). Per primary, a_lm(p, b)
+of a slice of primaries is compared as well. The batch is also checked by
+properties that hold at any size: each catalogue of the batch equals the same
+catalogue run alone, bit for bit, and the mixed path agrees with the FP64 path
+within the split-BF16 tolerance. A data + 5x randoms catalogue with
+data-minus-randoms weights checks every precision against the FP64 path at
+full size.
 """
 import sys
 
@@ -76,6 +79,60 @@ def test_alm_slice_400k_mixed(torch):
                           T.PREC_MIXED_BF16X3, 250_001)
     say(f"  a_lm slice rel err {err:.3e}")
     assert err < 1e-5
+
+
+def run_one(torch, P, box, edges, lmax, mults, prec):
+    h = T.Handle(box, edges, lmax, precision=prec)
+    h.build_grid(P)
+    h.alm_accumulate()
+    h.contract()
+    out = h.multipoles(mults)
+    h.sync()
+    n = h.pair_count()
+    h.close()
+    return out.cpu().numpy(), n
+
+
+def test_c2_catalogue_matches_oracle(torch):
+    """10^5 clustered points, 1000 Mpc/h, 10 bins over [20, 120], lmax 10,
+    L <= 2: all 59 multipoles of the FP32 and FP64 paths against the oracle."""
+    box, edges, lmax = 1000.0, np.linspace(20.0, 120.0, 11), 10
+    mults = O.all_multipoles(lmax, 2)
+    pos = zeldovich_host(torch, 100_000, box, 6.0, 0.8, C.catalogue_seed(1))
+    say("  oracle: 1e5-point catalogue")
+    ref, _, res = O.run(pos, box, edges, lmax, mults)
+    P = torch.from_numpy(pos).cuda()
+    for prec, tol in ((T.PREC_FP64, 1e-12), (T.PREC_FP32, 1e-5)):
+        got, n = run_one(torch, P, box, edges, lmax, mults, prec)
+        err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        say(f"  precision {prec}: pairs {n} (oracle {res.npairs}), rel err {err:.3e}")
+        assert n == res.npairs
+        assert err < tol
+
+
+def test_c3_catalogue_matches_oracle(torch):
+    """4x10^5 clustered points, 1500 Mpc/h, 12 bins over [10, 130], lmax 10,
+    L <= 4 (132 multipoles): the split-BF16 and FP64 paths against the oracle,
+    and split-BF16 against FP64."""
+    box, edges, lmax = 1500.0, np.linspace(10.0, 130.0, 13), 10
+    mults = O.all_multipoles(lmax, 4)
+    pos = zeldovich_host(torch, 400_000, box, 5.0, 0.8, C.catalogue_seed(2))
+    P = torch.from_numpy(pos).cuda()
+    mixed, n_mixed = run_one(torch, P, box, edges, lmax, mults, T.PREC_MIXED_BF16X3)
+    fp64, n_fp64 = run_one(torch, P, box, edges, lmax, mults, T.PREC_FP64)
+    assert n_mixed == n_fp64
+    err = float(np.abs(mixed - fp64).max() / np.abs(fp64).max())
+    say(f"  split-BF16 vs FP64 path rel err {err:.3e}")
+    assert err < 1e-4
+    say("  oracle: 4e5-point catalogue")
+    ref, _, res = O.run(pos, box, edges, lmax, mults)
+    assert n_fp64 == res.npairs
+    scale = np.abs(ref).max()
+    e64 = float(np.abs(fp64 - ref).max() / scale)
+    emx = float(np.abs(mixed - ref).max() / scale)
+    say(f"  vs oracle: FP64 rel err {e64:.3e}, split-BF16 rel err {emx:.3e}")
+    assert e64 < 1e-12
+    assert emx < 1e-4
 
 
 def test_data_minus_randoms_large(torch):
@@ -164,6 +221,17 @@ def test_batched_64_catalogues(torch):
     err = alm_slice_error(torch, pos0, box, edges, lmax, T.PREC_FP64, 1000)
     say(f"  catalogue 0 a_lm slice rel err {err:.3e}")
     assert err < 1e-12
+
+    # whole catalogues of the batch against the oracle: every multipole, both paths
+    for i in (1, 63):
+        say(f"  oracle: catalogue {i} ({int(sizes[i])} points)")
+        ref, _, _ = O.run(cats[i].cpu().numpy(), box, edges, lmax, mults)
+        scale = np.abs(ref).max()
+        e64 = float(np.abs(fp64[i] - ref).max() / scale)
+        emx = float(np.abs(mixed[i] - ref).max() / scale)
+        say(f"  catalogue {i}: FP64 batch rel err {e64:.3e}, split-BF16 batch rel err {emx:.3e}")
+        assert e64 < 1e-12
+        assert emx < 1e-4
 
 
 def test_isotropic_batch(torch):
