@@ -243,6 +243,37 @@ tpcf_status tpcf_edge_correct_isotropic(tpcf_handle h, int32_t n_ell, const doub
                                         double* d_out);
 
 /*
+ * Szapudi-Szalay estimator with explicit randoms (eq. (ssest)), anisotropic
+ * multipoles: edge correction of the tripolar multipoles by the random triplet
+ * counts. Let N and R be the triplet counts of a data-minus-randoms run
+ * (weights 1 and -N_D/N_R) and of a run on the randoms alone, each a function of
+ * the two sides' directions (r1, r2) in a bin pair (b1, b2), with coefficients
+ * N^m_{l1 l2} and R^m_{l1 l2} in the orthonormal basis Y_l1m(r1) conj(Y_l2m(r2))
+ * (the exported NNN^m of tpcf_contract, each divided by its analytic RRR). The
+ * estimator N = zeta R, taken at every pair of directions, gives
+ *   N^m_{l1 l2} = sum zeta^{m'}_{l1' l2'} R^{m-m'}_{l1'' l2''} g(l1 m; l1' m'; l1'') g(l2 m; l2' m'; l2''),
+ *   g(l m; l' m'; l'') = integral of conj(Y_lm) Y_l'm' Y_l'',m-m' over the sphere,
+ * with every l truncated at the handle's lmax; it is solved for zeta at every
+ * (b1, b2) in FP64 (Gaussian elimination with partial pivoting). Only real
+ * coefficients enter (the export holds the real parts): the reflection-
+ * symmetric sector, whose coefficients satisfy X^{-m} = X^m.
+ *  d_nnn_N, d_nnn_R: device, (lmax+1)^3 x nbins x nbins float64 each, the
+ *            exports of tpcf_contract of the two runs, made on handles with
+ *            this handle's box, bins and lmax (not checked).
+ *  n_data_N, n_data_R: N_D of the data-minus-randoms run and N_R of the randoms
+ *            run (their RRR normalisations), >= 3.
+ *  h_l1l2L, n_mult, d_out: multipoles of zeta as for tpcf_multipoles
+ *            (n_mult x nbins x nbins), or d_out = NULL for none.
+ *  d_zeta:   NULL, or device (lmax+1)^3 x nbins x nbins float64 receiving the
+ *            corrected coefficients zeta^m in the export layout.
+ *  lmax <= 10 (TPCF_ERR_RANGE otherwise). A singular system gives
+ *  TPCF_ERR_RANGE. Synchronises the stream.
+ */
+tpcf_status tpcf_edge_correct(tpcf_handle h, const double* d_nnn_N, int64_t n_data_N, const double* d_nnn_R,
+                              int64_t n_data_R, int32_t n_mult, const int32_t* h_l1l2L, double* d_out,
+                              double* d_zeta);
+
+/*
  * Covariance step of Sec. 4.3, for measurements of a suite of mock catalogues.
  *
  * tpcf_triangle_index: host helper building a 3PCF data vector. For each

@@ -11,7 +11,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/tpcf.h"
@@ -25,9 +27,7 @@ using namespace tpcf;
 
 namespace {
 
-constexpr uint32_t kMagic = 0x74706366u;  // "tpcf"
 constexpr int kStages = 6;                // timed stages (tpcf_stage_times)
-constexpr uint32_t kDead = 0xdeadbeefu;
 const double kPi = 3.14159265358979323846;
 
 struct DevBuf {
@@ -50,7 +50,6 @@ struct Chunk {
 }  // namespace
 
 struct tpcf_handle_s {
-    uint32_t magic = kMagic;
     tpcf_config cfg{};
     std::vector<double> edges;
     int device = 0;
@@ -114,7 +113,8 @@ struct tpcf_handle_s {
     // covariance
     DevBuf d_covx, d_covoff, d_covflag, d_covpart;
     // edge correction
-    DevBuf d_edgeT;
+    DevBuf d_edgeT, d_egaunt, d_eunits, d_errr, d_ecoef, d_eM, d_erhs, d_ezeta, d_emult;
+    int egaunt_lmax = -1;  // lmax of the Gaunt table held in d_egaunt
     // device address of the static scratch of the allocation-free covariance
     void* cov_scratch = nullptr;
 
@@ -132,7 +132,21 @@ tpcf_status fail(tpcf_handle h, tpcf_status st, const std::string& msg) {
     return st;
 }
 
-bool alive(tpcf_handle h) { return h && h->magic == kMagic; }
+// Live handles. A handle is checked by looking its address up here, never by
+// reading through it, so a destroyed (freed) or foreign pointer is refused
+// without touching its memory. The set is never destroyed: handles may still
+// be released by static destructors at process exit.
+std::mutex g_live_mu;
+std::unordered_set<const void*>& live_handles() {
+    static auto* s = new std::unordered_set<const void*>();
+    return *s;
+}
+
+bool alive(tpcf_handle h) {
+    if (!h) return false;
+    std::lock_guard<std::mutex> lock(g_live_mu);
+    return live_handles().count(h) != 0;
+}
 
 tpcf_status hip_fail(tpcf_handle h, hipError_t e, const char* what) {
     return fail(h, TPCF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -933,6 +947,53 @@ tpcf_status pair_pass(tpcf_handle h, bool contract_now) {
     return TPCF_OK;
 }
 
+// Polar part of Y_lm for any sign of m: Y_lm = Theta_lm(cos t) e^{i m phi},
+// Theta_lm = (-1)^m N_lm (1-z^2)^{m/2} d^m P_l/dz^m for m >= 0 (Condon-Shortley)
+// and Theta_l,-m = (-1)^m Theta_lm (from Y_l,-m = (-1)^m conj(Y_lm)).
+// th[(l * (2 lmax + 1)) + m + lmax] at one z.
+void polar_parts(int lmax, double z, std::vector<double>& th) {
+    const int S2 = 2 * lmax + 1;
+    th.assign((size_t)(lmax + 1) * S2, 0.0);
+    std::vector<double> R;
+    for (int m = 0; m <= lmax; ++m) {
+        r_chain(lmax, m, z, R);
+        const double sm = std::pow(std::max(0.0, 1.0 - z * z), 0.5 * m);
+        for (int l = m; l <= lmax; ++l) {
+            const double nbar = norm_lm(l, m) * gamma_lm(l, m) * R[l] * sm;
+            th[(size_t)l * S2 + m + lmax] = (m & 1) ? -nbar : nbar;
+            th[(size_t)l * S2 - m + lmax] = nbar;
+        }
+    }
+}
+
+// g(l, m; l', m'; l'') = integral of conj(Y_lm) Y_l'm' Y_l'',m-m' over the
+// sphere = 2 pi integral of Theta_lm Theta_l'm' Theta_l'',m-m' dz, by 64-point
+// Gauss-Legendre quadrature (the integrand is a polynomial of degree at most
+// 3 lmax). Layout [l][m >= 0][l'][m' + lmax][l''], exact zeros where the
+// triangle rule, parity or |m - m'| > l'' forbid the coupling.
+void build_edge_gaunt(int lmax, std::vector<double>& g) {
+    const int S = lmax + 1, S2 = 2 * lmax + 1;
+    g.assign((size_t)S * S * S * S2 * S, 0.0);
+    std::vector<double> x, w, th;
+    gauss_legendre(64, x, w);
+    std::vector<std::vector<double>> T(x.size());
+    for (size_t i = 0; i < x.size(); ++i) polar_parts(lmax, x[i], T[i]);
+    for (int l = 0; l <= lmax; ++l)
+        for (int m = 0; m <= l; ++m)
+            for (int lp = 0; lp <= lmax; ++lp)
+                for (int mp = -lp; mp <= lp; ++mp)
+                    for (int lpp = 0; lpp <= lmax; ++lpp) {
+                        const int mpp = m - mp;
+                        if (std::abs(mpp) > lpp || lpp < std::abs(l - lp) || lpp > l + lp || ((l + lp + lpp) & 1))
+                            continue;
+                        double v = 0.0;
+                        for (size_t i = 0; i < x.size(); ++i)
+                            v += w[i] * T[i][(size_t)l * S2 + m + lmax] * T[i][(size_t)lp * S2 + mp + lmax] *
+                                 T[i][(size_t)lpp * S2 + mpp + lmax];
+                        g[((((size_t)l * S + m) * S + lp) * S2 + mp + lmax) * S + lpp] = 2.0 * kPi * v;
+                    }
+}
+
 tpcf_status validate_config(const tpcf_config* c) {
     if (!c) return TPCF_ERR_ARG;
     if (!(c->box > 0.0) || !std::isfinite(c->box)) return TPCF_ERR_ARG;
@@ -971,6 +1032,10 @@ tpcf_status tpcf_create(const tpcf_config* cfg, int device, void* hip_stream, tp
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TPCF_ERR_DEVICE;
     if (hipSetDevice(device) != hipSuccess) return TPCF_ERR_DEVICE;
     tpcf_handle h = new tpcf_handle_s();
+    {
+        std::lock_guard<std::mutex> lock(g_live_mu);
+        live_handles().insert(h);
+    }
     h->cfg = *cfg;
     h->edges.assign(cfg->h_edges, cfg->h_edges + cfg->nbins + 1);
     h->cfg.h_edges = h->edges.data();
@@ -999,7 +1064,12 @@ tpcf_status tpcf_create(const tpcf_config* cfg, int device, void* hip_stream, tp
 }
 
 void tpcf_destroy(tpcf_handle h) {
-    if (!alive(h)) return;
+    {
+        // unregister first: a second destroy, or a call racing this one, sees
+        // a dead handle without reading it
+        std::lock_guard<std::mutex> lock(g_live_mu);
+        if (!h || live_handles().erase(h) == 0) return;
+    }
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
     for (Timer& t : h->timers) {
@@ -1013,9 +1083,9 @@ void tpcf_destroy(tpcf_handle h) {
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag,
                      &h->d_xiq, &h->d_xicoef, &h->d_xirr, &h->d_xiruns, &h->d_covx, &h->d_covoff,
-                     &h->d_covflag, &h->d_covpart, &h->d_edgeT};
+                     &h->d_covflag, &h->d_covpart, &h->d_edgeT, &h->d_egaunt, &h->d_eunits, &h->d_errr,
+                     &h->d_ecoef, &h->d_eM, &h->d_erhs, &h->d_ezeta, &h->d_emult};
     for (DevBuf* b : all) release(h, *b);
-    h->magic = kDead;
     delete h;
 }
 
@@ -1048,6 +1118,8 @@ tpcf_status tpcf_alm_accumulate(tpcf_handle h) {
     if (st != TPCF_OK) return st;
     if ((st = plan_chunks(h)) != TPCF_OK) return st;
     const bool single = h->chunks.size() == 1;
+    // the step calls keep every self-moment order (h->self_lo is false here)
+    h->self_cut = h->self_lo;
     if ((st = pair_pass(h, !single)) != TPCF_OK) return st;
     h->alm_kept = single;
     h->contracted_in_pass = !single;
@@ -1518,6 +1590,94 @@ tpcf_status tpcf_edge_correct_isotropic(tpcf_handle h, int32_t n_ell, const doub
     HIPCHK(hipMemcpyAsync(&bad, h->d_covflag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     if (bad) return fail(h, TPCF_ERR_RANGE, "singular coupling matrix (random multipoles)");
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_edge_correct(tpcf_handle h, const double* d_nnn_N, int64_t n_data_N, const double* d_nnn_R,
+                              int64_t n_data_R, int32_t n_mult, const int32_t* h_l1l2L, double* d_out,
+                              double* d_zeta) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!d_nnn_N || !d_nnn_R) return fail(h, TPCF_ERR_ARG, "NULL triplet-count coefficients");
+    if (!d_out && !d_zeta) return fail(h, TPCF_ERR_ARG, "neither multipoles nor coefficients requested");
+    if (n_data_N < 3 || n_data_R < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3 for both runs");
+    if (h->lmax > kMaxEdgeLmax) return fail(h, TPCF_ERR_RANGE, "the anisotropic edge correction needs lmax <= 10");
+    tpcf_status st;
+    if (d_out) {
+        if ((st = check_mults(h, n_mult, h_l1l2L)) != TPCF_OK) return st;
+    } else {
+        n_mult = 0;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    const int lmax = h->lmax, S = lmax + 1, nb = h->nb, nsys = nb * nb;
+    std::vector<int4> units;
+    for (int m = 0; m <= lmax; ++m)
+        for (int l1 = m; l1 <= lmax; ++l1)
+            for (int l2 = m; l2 <= lmax; ++l2) units.push_back(make_int4(l1, l2, m, 0));
+    const int n = (int)units.size();
+    if (h->egaunt_lmax != lmax) {
+        std::vector<double> g;
+        build_edge_gaunt(lmax, g);
+        if ((st = upload(h, h->d_egaunt, g.data(), sizeof(double) * g.size())) != TPCF_OK) return st;
+        h->egaunt_lmax = lmax;
+    }
+    // 1 / RRR of both runs (analytic periodic-box counts), [run][b1 nb + b2]
+    std::vector<double> irrr(2 * (size_t)nsys);
+    const double L = h->cfg.box, L6 = L * L * L * L * L * L;
+    for (int r = 0; r < 2; ++r) {
+        const double nd = (double)(r == 0 ? n_data_N : n_data_R);
+        for (int b1 = 0; b1 < nb; ++b1)
+            for (int b2 = 0; b2 < nb; ++b2)
+                irrr[(size_t)r * nsys + b1 * nb + b2] = L6 / (nd * (nd - 1.0) * (nd - 2.0) * h->vol[b1] * h->vol[b2]);
+    }
+    // TripoSH weight of zeta^m in c_{l1 l2 L}: 8 pi^2 (2L+1) q(l1, l2, m, L), doubled for m > 0
+    // (zeta^-m = zeta^m), as in the multipoles of the contraction
+    std::vector<double> coef((size_t)std::max(n_mult, 1) * S, 0.0);
+    const bool lit = (h->cfg.flags & TPCF_F_PAPER_LITERAL) != 0;
+    for (int t = 0; t < n_mult; ++t) {
+        const int l1 = h_l1l2L[3 * t], l2 = h_l1l2L[3 * t + 1], LL = h_l1l2L[3 * t + 2];
+        const double f = lit ? 4.0 * kPi / std::sqrt((2.0 * l1 + 1.0) * (2.0 * l2 + 1.0)) : 1.0;
+        for (int m = 0; m <= std::min(l1, l2); ++m)
+            coef[(size_t)t * S + m] = 8.0 * kPi * kPi * (2.0 * LL + 1.0) * qv(h, l1, l2, m, LL) * (m > 0 ? 2.0 : 1.0) * f;
+    }
+    if ((st = upload(h, h->d_eunits, units.data(), sizeof(int4) * units.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_errr, irrr.data(), sizeof(double) * irrr.size())) != TPCF_OK) return st;
+    if ((st = upload(h, h->d_ecoef, coef.data(), sizeof(double) * coef.size())) != TPCF_OK) return st;
+    if (n_mult > 0 && (st = upload(h, h->d_emult, h_l1l2L, sizeof(int) * 3 * n_mult)) != TPCF_OK) return st;
+    const int64_t nz = (int64_t)S * S * S * nsys;
+    if ((st = ensure(h, h->d_eM, sizeof(double) * (size_t)nsys * n * n)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_erhs, sizeof(double) * (size_t)nsys * n)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_ezeta, sizeof(double) * (size_t)nz)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_covflag, sizeof(int))) != TPCF_OK) return st;
+    HIPCHK(launch_fill_i32(P<int>(h->d_covflag), 1, 0, h->stream));
+    HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_ezeta), nz, 0ull, h->stream));
+    EdgeArgs a{};
+    a.N = d_nnn_N;
+    a.R = d_nnn_R;
+    a.inv_rrr_N = P<double>(h->d_errr);
+    a.inv_rrr_R = P<double>(h->d_errr) + nsys;
+    a.gaunt = P<double>(h->d_egaunt);
+    a.units = P<int4>(h->d_eunits);
+    a.n = n;
+    a.lmax = lmax;
+    a.nsys = nsys;
+    a.M = P<double>(h->d_eM);
+    a.rhs = P<double>(h->d_erhs);
+    a.zeta = P<double>(h->d_ezeta);
+    a.bad = P<int>(h->d_covflag);
+    a.n_mult = n_mult;
+    a.mult = n_mult > 0 ? P<int>(h->d_emult) : nullptr;
+    a.coef = P<double>(h->d_ecoef);
+    a.out = d_out;
+    Timer t;
+    t_begin(h, 4, t);
+    HIPCHK(launch_edge_aniso(a, h->stream));
+    t_end(h, t);
+    if (d_zeta)
+        HIPCHK(hipMemcpyAsync(d_zeta, h->d_ezeta.p, sizeof(double) * (size_t)nz, hipMemcpyDeviceToDevice, h->stream));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->d_covflag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (bad) return fail(h, TPCF_ERR_RANGE, "singular coupling matrix (random triplet counts)");
     return TPCF_OK;
 }
 

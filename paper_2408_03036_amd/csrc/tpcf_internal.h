@@ -272,6 +272,29 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_edge_iso(const double* N, const double* R, const double* T, int nl, int nbb, double* out, int* bad,
                            hipStream_t s);
 
+// Anisotropic edge correction (tpcf_edge.hip): one n x n real system per
+// (b1, b2), n = number of (l1, l2, m) with 0 <= m <= l1, l2 <= lmax.
+constexpr int kMaxEdgeLmax = 10;
+constexpr int kMaxEdgeUnknowns = 506;  // n at lmax = 10
+struct EdgeArgs {
+    const double* N;         // [(lmax+1)^3][nsys] NNN^m export of the data-minus-randoms run
+    const double* R;         // the same of the randoms run
+    const double* inv_rrr_N; // [nsys] 1 / RRR of each run
+    const double* inv_rrr_R;
+    const double* gaunt;     // [S][S][S][2S-1][S] g(l, m; l', m'; l'') (S = lmax + 1, m >= 0, |m'| <= lmax)
+    const int4* units;       // [n] (l1, l2, m) of each unknown
+    int n, lmax, nsys;       // nsys = nbins^2, system q = b1 nbins + b2
+    double* M;               // [nsys][n][n] workspace
+    double* rhs;             // [nsys][n] workspace: right-hand sides, then solutions
+    double* zeta;            // [(lmax+1)^3][nsys] corrected coefficients (zero-filled beforehand)
+    int* bad;                // set when a system is singular
+    int n_mult;
+    const int* mult;         // [n_mult * 3]
+    const double* coef;      // [n_mult][S] TripoSH weight of zeta^m
+    double* out;             // [n_mult][nsys]
+};
+hipError_t launch_edge_aniso(const EdgeArgs& a, hipStream_t s);
+
 struct NnnArgs {
     const double* G;         // [gsize] one catalogue
     const int64_t* goff;

@@ -850,7 +850,9 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         }
     }
     if (!active) return;
-    if constexpr (UNIT && AC::MLO == 0) acc.a[0 - AC::V0] = (T)n;  // exact: lists hold < 2^24 hits
+    // the degree-0 sum is the list length: exact below 2^24 hits in FP32, and
+    // above that rounded to FP32 like any FP32 sum (lists hold at most 2^27)
+    if constexpr (UNIT && AC::MLO == 0) acc.a[0 - AC::V0] = (T)n;
     if constexpr (UNIT && AC::MLO == 0 && AC::SELF) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) acc.s[l] = acc.a[l - AC::V0];

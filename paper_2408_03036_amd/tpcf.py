@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtpcf.so")
+# TPCF_LIBRARY selects another build of the library (for example the
+# host-sanitized _build_san/libtpcf_san.so of build.py); default: the in-tree libtpcf.so
+LIB_PATH = os.environ.get("TPCF_LIBRARY") or os.path.join(HERE, "libtpcf.so")
 
 TPCF_OK = 0
 TPCF_ERR_ARG = -1
@@ -36,7 +38,7 @@ EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_alm_accumulate", "tpcf_get_alm", "tpcf_contract", "tpcf_multipoles",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
            "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles", "tpcf_triangle_index",
-           "tpcf_covariance", "tpcf_covariance_noalloc", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic",
+           "tpcf_covariance", "tpcf_covariance_noalloc", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic", "tpcf_edge_correct",
            "tpcf_autotune"]
 
 
@@ -110,6 +112,8 @@ def load():
     lib.tpcf_percival_m1.restype = st
     lib.tpcf_edge_correct_isotropic.argtypes = [vp, i32, vp, vp, vp]
     lib.tpcf_edge_correct_isotropic.restype = st
+    lib.tpcf_edge_correct.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp, vp]
+    lib.tpcf_edge_correct.restype = st
     lib.tpcf_autotune.argtypes = [vp, vp, vp, i64, i64, i32, ctypes.POINTER(i32), vp]
     lib.tpcf_autotune.restype = st
     _lib = lib
@@ -278,6 +282,31 @@ class Handle:
         out = torch.empty_like(N)
         self._chk(self.lib.tpcf_edge_correct_isotropic(self.h, N.shape[0], _ptr(N), _ptr(R), _ptr(out)))
         return out
+
+    def edge_correct(self, nnn_N, n_data_N, nnn_R, n_data_R, mults=None, want_zeta=False):
+        """Anisotropic edge correction from the NNN^m exports of a data-minus-
+        randoms run and of a randoms run ([m][l1][l2][b1][b2] float64 on the
+        GPU, from contract(export=True)); returns (multipoles or None, zeta^m
+        or None)."""
+        import torch
+        _check_dev(nnn_N, torch.float64, "nnn_N")
+        _check_dev(nnn_R, torch.float64, "nnn_R")
+        s1 = self.lmax + 1
+        shape = (s1, s1, s1, self.nbins, self.nbins)
+        if tuple(nnn_N.shape) != shape or tuple(nnn_R.shape) != shape:
+            raise ValueError(f"the exports must be {shape}")
+        out = zeta = None
+        tr = None
+        if mults is not None:
+            tr = np.ascontiguousarray(np.array(mults, dtype=np.int32).reshape(-1, 3))
+            out = torch.empty((tr.shape[0], self.nbins, self.nbins), dtype=torch.float64, device=nnn_N.device)
+        if want_zeta:
+            zeta = torch.empty(shape, dtype=torch.float64, device=nnn_N.device)
+        self._chk(self.lib.tpcf_edge_correct(self.h, _ptr(nnn_N), int(n_data_N), _ptr(nnn_R), int(n_data_R),
+                                             0 if tr is None else tr.shape[0],
+                                             None if tr is None else ctypes.c_void_p(tr.ctypes.data),
+                                             _ptr(out), _ptr(zeta)))
+        return out, zeta
 
     # -- covariance over mock catalogues (Sec. 4.3) -----------------------
     def covariance(self, src, n_d=None, offsets=None):

@@ -113,6 +113,14 @@ def test_host_helpers_match_oracle(lib):
         assert off.tolist() == ref, (eta, rmin)
     for nm, nd, npar in [(3000, 336, 6), (298, 48, 4), (100, 90, 3)]:
         assert abs(T.percival_m1(nm, nd, npar) - V.percival_m1(nm, nd, npar)) < 1e-14
+    # and with the exact fractions evaluated by hand (tests/golden/percival_m1.json)
+    import json
+    import os
+    from fractions import Fraction
+    with open(os.path.join(os.path.dirname(__file__), "golden", "percival_m1.json")) as f:
+        for g in json.load(f)["values"]:
+            m1 = float(Fraction(*g["m1"]))
+            assert abs(T.percival_m1(g["n_mocks"], g["n_d"], g["n_params"]) - m1) <= 4 * np.spacing(m1)
     with pytest.raises(T.TpcfError):
         T.triangle_index([0.0, 1.0, 3.0], 1, 0.0, [0])  # unequal bins
     with pytest.raises(T.TpcfError):
@@ -122,3 +130,20 @@ def test_host_helpers_match_oracle(lib):
     assert lib.tpcf_precision_matrix(None, 5, None, 10, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_autotune(None, None, None, 10, 10, 0, None, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_edge_correct_isotropic(None, 3, None, None, None) == T.TPCF_ERR_ARG
+
+
+def test_foreign_and_dead_handles_are_refused_unread(lib):
+    """Handles are checked against the library's set of live handles, never by
+    reading through the pointer: a pointer that was never a handle (here the
+    address of a host buffer filled with garbage) is refused by every call, and
+    destroying it is a no-op. (A double destroy and a use after destroy of a
+    real handle are tested on the GPU.)"""
+    junk = (ctypes.c_ubyte * 4096)(*([0xAB] * 4096))
+    bogus = ctypes.c_void_p(ctypes.addressof(junk))
+    assert lib.tpcf_sync(bogus) == T.TPCF_ERR_ARG
+    assert lib.tpcf_alm_accumulate(bogus) == T.TPCF_ERR_ARG
+    assert lib.tpcf_contract(bogus, None) == T.TPCF_ERR_ARG
+    assert b"invalid or destroyed" in lib.tpcf_last_error(bogus)
+    lib.tpcf_destroy(bogus)
+    lib.tpcf_destroy(bogus)
+    assert bytes(junk) == bytes([0xAB] * 4096)  # nothing was written through it

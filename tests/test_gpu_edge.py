@@ -87,3 +87,108 @@ def test_explicit_randoms_chain(torch, prec, tol):
     err = float(np.abs(got - ref).max() / np.abs(ref).max())
     say(f"  explicit-randoms chain rel err {err:.2e}")
     assert err < tol
+
+
+# ------------------------------------------------------------------ anisotropic (tripolar) correction
+
+
+def _synthetic_exports(rng, lmax, nb, scale):
+    """Real coefficients [m][l1][l2][b1][b2] (zero where l < m) of a function
+    near the constant 1 (coefficient 4 pi at l1 = l2 = m = 0) plus noise."""
+    s1 = lmax + 1
+    X = np.zeros((s1, s1, s1, nb, nb))
+    for m in range(s1):
+        for l1 in range(m, s1):
+            for l2 in range(m, s1):
+                X[m, l1, l2] = rng.uniform(-scale, scale, (nb, nb))
+    X[0, 0, 0] += 4.0 * np.pi
+    return X
+
+
+@pytest.mark.parametrize("lmax,nb", [(2, 3), (4, 2), (6, 2)])
+def test_anisotropic_correction_matches_oracle(torch, lmax, nb):
+    """The kernel (quadrature Gaunt couplings, pivoted FP64 elimination) against
+    the oracle's solve (3j couplings, numpy) on synthetic normalised counts."""
+    rng = np.random.default_rng(lmax * 10 + nb)
+    box, edges = 100.0, np.linspace(2.0, 20.0, nb + 1)
+    nD, nR = 5000, 50000
+    Nn = _synthetic_exports(rng, lmax, nb, 0.5)
+    Rn = _synthetic_exports(rng, lmax, nb, 0.05)
+    # the exports are unnormalised: multiply by each run's RRR
+    NN = Nn * O.rrr(nD, box, edges)[None, None, None]
+    RR = Rn * O.rrr(nR, box, edges)[None, None, None]
+    mults = O.all_multipoles(lmax, 2)
+    h = T.Handle(box, edges, lmax, precision=T.PREC_FP64)
+    out, zeta = h.edge_correct(torch.from_numpy(NN).cuda(), nD, torch.from_numpy(RR).cuda(), nR, mults,
+                               want_zeta=True)
+    got_z = zeta.cpu().numpy()
+    got_c = out.cpu().numpy()
+    h.close()
+    ref_z = O.edge_correct_anisotropic(Nn.astype(np.complex128), Rn.astype(np.complex128))
+    assert np.abs(ref_z.imag).max() == 0.0
+    ez = float(np.abs(got_z - ref_z.real).max() / np.abs(ref_z.real).max())
+    ref_c, _ = O.multipoles_from_coefficients(ref_z, lmax, mults)
+    ec = float(np.abs(got_c - ref_c).max() / np.abs(ref_c).max())
+    say(f"  anisotropic correction lmax={lmax} nb={nb}: zeta rel err {ez:.2e}, multipoles {ec:.2e}")
+    assert ez < 1e-12
+    assert ec < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(T.PREC_FP64, 1e-10), (T.PREC_FP32, 1e-5)])
+def test_anisotropic_explicit_randoms_chain(torch, prec, tol):
+    """1,000 clustered data points and 10x randoms in a 150 Mpc/h box, 4 bins
+    over [8, 40], lmax 3, L <= 2: the per-m counts of the data-minus-randoms
+    and randoms runs (tpcf_contract exports), corrected; the oracle runs the
+    same chain on the real parts of its per-m counts."""
+    box, edges, lmax = 150.0, np.linspace(8.0, 40.0, 5), 3
+    nd, nr = 1000, 10000
+    D = C.zeldovich(nd, box, 4.0, 0.8, C.catalogue_seed(81), grid=32)
+    Rp = C.randoms(nr, box, C.randoms_seed(81))
+    pos = np.vstack([D, Rp])
+    w = C.dr_weights(nd, nr)
+    mults = O.all_multipoles(lmax, 2)
+    say("  oracle: data-minus-randoms and randoms runs")
+    resN = O.estimate(pos, box, edges, lmax, w=w)
+    resR = O.estimate(Rp, box, edges, lmax)
+    zN = resN.nnn.real / O.rrr(nd, box, edges)[None, None, None]
+    zR = resR.nnn.real / O.rrr(nr, box, edges)[None, None, None]
+    ref_z = O.edge_correct_anisotropic(zN, zR)
+    ref, _ = O.multipoles_from_coefficients(ref_z, lmax, mults)
+
+    def export(p, wt):
+        h = T.Handle(box, edges, lmax, precision=prec)
+        h.build_grid(torch.from_numpy(p).cuda(), None if wt is None else torch.from_numpy(wt).cuda(), nd)
+        h.alm_accumulate()
+        nnn = h.contract(export=True)
+        h.sync()
+        return h, nnn
+
+    hN, NN = export(pos, w)
+    hR, RR = export(Rp, None)
+    got, _ = hN.edge_correct(NN, nd, RR, nr, mults)
+    got = got.cpu().numpy()
+    hN.close()
+    hR.close()
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"  anisotropic explicit-randoms chain rel err {err:.2e}")
+    assert err < tol
+
+
+def test_anisotropic_correction_errors(torch):
+    h = T.Handle(100.0, np.linspace(1.0, 20.0, 3), 2)
+    s = (3, 3, 3, 2, 2)
+    Z = torch.zeros(s, dtype=torch.float64).cuda()
+    with pytest.raises(T.TpcfError) as e:
+        h.edge_correct(Z + 1.0, 100, Z, 100, [(0, 0, 0)])  # random counts all zero: singular
+    assert e.value.status == T.TPCF_ERR_RANGE
+    with pytest.raises(T.TpcfError) as e:
+        h.edge_correct(Z, 2, Z, 100, [(0, 0, 0)])  # n_data < 3
+    assert e.value.status == T.TPCF_ERR_ARG
+    h.close()
+    h = T.Handle(100.0, np.linspace(1.0, 20.0, 3), 11)
+    s = (12, 12, 12, 2, 2)
+    Z = torch.zeros(s, dtype=torch.float64).cuda()
+    with pytest.raises(T.TpcfError) as e:
+        h.edge_correct(Z, 100, Z, 100, [(0, 0, 0)])  # lmax above 10
+    assert e.value.status == T.TPCF_ERR_RANGE
+    h.close()

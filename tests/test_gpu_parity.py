@@ -11,6 +11,7 @@ bin b). Its 1e-4 bound is checked on the dense configuration it is meant for;
 the sparse C1 anchor (0.13 neighbours per primary in its first bin) is
 checked with the 6-product split.
 """
+import ctypes
 import math
 import sys
 
@@ -361,6 +362,25 @@ def test_out_of_order_calls(torch):
         h.multipoles([(1, 0, 0)])
     assert e.value.status == T.TPCF_ERR_ARG
     h.close()
+
+
+def test_double_destroy_and_use_after_destroy(torch):
+    """A destroyed handle is refused by every call (looked up in the library's
+    set of live handles, not read), and destroying it again is a no-op."""
+    h = T.Handle(50.0, np.array([1.0, 5.0]), 2)
+    raw = ctypes.c_void_p(h.h.value)
+    lib = h.lib
+    assert lib.tpcf_sync(raw) == T.TPCF_OK
+    lib.tpcf_destroy(raw)
+    h.h = None
+    lib.tpcf_destroy(raw)
+    assert lib.tpcf_sync(raw) == T.TPCF_ERR_ARG
+    assert lib.tpcf_alm_accumulate(raw) == T.TPCF_ERR_ARG
+    assert b"invalid or destroyed" in lib.tpcf_last_error(raw)
+    # a new handle works after the dead one
+    h2 = T.Handle(50.0, np.array([1.0, 5.0]), 2)
+    h2.sync()
+    h2.close()
 
 
 def test_workspace_limit_enforced(torch):
