@@ -57,6 +57,19 @@ def contraction_flop(sizes, nb, lmax):
     return tot
 
 
+def needed_contraction_flop(sizes, nb, lmax, Lmax):
+    """The part of the dense contraction work that multipoles with L <= Lmax
+    read: the (l1, l2, m) blocks with |l1 - l2| <= Lmax, each 2 K_rows nb^2."""
+    per_p = 0.0
+    for m in range(lmax + 1):
+        rows = 1 if m == 0 else 2
+        for l1 in range(m, lmax + 1):
+            for l2 in range(m, lmax + 1):
+                if abs(l1 - l2) <= Lmax:
+                    per_p += 2.0 * rows * nb * nb
+    return per_p * float(sum(int(p) for p in sizes))
+
+
 def all_multipoles(lmax, Lmax):
     out = []
     for l1 in range(lmax + 1):
@@ -112,30 +125,108 @@ def measured_traffic(kernel_sources):
     return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
-def cpu_baseline(pos_np, box, edges, lmax, target_s=15.0):
-    """Times the FP64 CPU oracle on a bounded sample of primaries of one
-    catalogue (all host threads), scaled to pairs/s."""
-    from oracle import oracle as O
-    nthr = os.cpu_count() or 1
+def host_info():
+    """The host the CPU baseline runs on: logical CPUs, CPUs this process may
+    run on, the OpenMP thread setting and the CPU model."""
+    model = None
     try:
-        nthr = len(os.sched_getaffinity(0))
-    except Exception:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
         pass
-    nthr = min(nthr, 16)
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except Exception:
+        aff = None
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": model}
+
+
+def oracle_threads():
+    """Threads for the oracle: OMP_NUM_THREADS when it is set (the CPU share
+    the host gives this job), else every CPU this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env), "OMP_NUM_THREADS"
+    try:
+        return len(os.sched_getaffinity(0)), "affinity"
+    except Exception:
+        return os.cpu_count() or 1, "cpu_count"
+
+
+def _oracle_sample(O, pos_np, box, edges, lmax, nthr, target_s, w=None):
+    """Times the oracle on the first primaries of a catalogue, sized for about
+    target_s seconds; returns (pairs/s, primaries, pairs, seconds)."""
     n = pos_np.shape[0]
-    probe = min(n, 256)
+    probe = min(n, max(16, 16 * nthr))
     t0 = time.perf_counter()
-    r = O.estimate(pos_np, box, edges, lmax, prim_first=0, prim_count=probe, nthreads=nthr)
+    r = O.estimate(pos_np, box, edges, lmax, w=w, prim_first=0, prim_count=probe, nthreads=nthr)
     t1 = time.perf_counter() - t0
     rate = r.npairs / max(t1, 1e-9)
     per_prim = r.npairs / probe
     count = int(min(n, max(probe, target_s * rate / max(per_prim, 1.0))))
     t0 = time.perf_counter()
-    r = O.estimate(pos_np, box, edges, lmax, prim_first=0, prim_count=count, nthreads=nthr)
+    r = O.estimate(pos_np, box, edges, lmax, w=w, prim_first=0, prim_count=count, nthreads=nthr)
     t1 = time.perf_counter() - t0
-    return {"value": r.npairs / t1, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
-            "sample": f"{count} primaries of catalogue 0 ({r.npairs} pairs, full estimator incl. "
-                      f"NNN accumulation) in {t1:.1f} s"}
+    return r.npairs / t1, count, r.npairs, t1
+
+
+def executed_flop(kernel_sources):
+    """FP32 FLOP the harmonic kernel executes per pair, from the
+    SQ_INSTS_VALU_FLOPS_FP32 counter summarised in profiles/ (None once the
+    sources differ from the ones it was taken on)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_pair_alm_batched64_lmax10_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if "executed_fp32_flop_per_pair" not in rec:
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", kernel_sources):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return {"per_pair": rec["executed_fp32_flop_per_pair"], "summary": rec.get("counters_summary")}
+
+
+def build_info():
+    """Identifies the build that ran: the git commit where the tree has one,
+    and a hash of the library's sources (present on every copy of the tree)."""
+    import hashlib
+    import subprocess
+    sha = None
+    try:
+        sha = subprocess.run(["git", "rev-parse", "--short=12", "HEAD"], cwd=ROOT, capture_output=True,
+                             text=True, timeout=10).stdout.strip() or None
+    except Exception:
+        pass
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2408_03036_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return {"git_sha": sha, "csrc_sha256": h.hexdigest()[:16]}
+
+
+def cpu_baseline(pos_np, box, edges, lmax, target_s=15.0, target_1t=5.0, w=None, what="catalogue 0"):
+    """Times the FP64 CPU oracle (the full estimator including the NNN
+    accumulation) on a bounded sample of primaries of one catalogue: with the
+    host's threads, and with one thread for the per-core rate; pairs/s."""
+    from oracle import oracle as O
+    nthr, src = oracle_threads()
+    rate, count, npairs, t1 = _oracle_sample(O, pos_np, box, edges, lmax, nthr, target_s, w)
+    rate1, count1, npairs1, t11 = _oracle_sample(O, pos_np, box, edges, lmax, 1, target_1t, w)
+    return {"value": rate, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{count} primaries of {what} ({npairs} pairs, full estimator incl. "
+                      f"NNN accumulation) in {t1:.1f} s on {nthr} threads ({src})",
+            "value_1thread": rate1,
+            "sample_1thread": f"{count1} primaries ({npairs1} pairs) in {t11:.1f} s on 1 thread",
+            "host": host_info()}
 
 
 # Algorithmic FP32 work per counted pair: separation (3), r^2 (5), r (1),
@@ -148,11 +239,7 @@ def xi_cpu_baseline(pos_np, box, edges, nmu, target_s=15.0):
     points are in random order, so the first n are a uniform subsample),
     sized for about target_s seconds; pairs/s."""
     from oracle import oracle as O
-    try:
-        nthr = len(os.sched_getaffinity(0))
-    except Exception:
-        nthr = os.cpu_count() or 1
-    nthr = min(nthr, 16)
+    nthr, src = oracle_threads()
     n = min(pos_np.shape[0], 50_000)
     t0 = time.perf_counter()
     npairs = int(O.xi_counts(pos_np[:n], box, edges, nmu, nthreads=nthr).sum())
@@ -163,7 +250,9 @@ def xi_cpu_baseline(pos_np, box, edges, nmu, target_s=15.0):
     npairs = int(O.xi_counts(pos_np[:n2], box, edges, nmu, nthreads=nthr).sum())
     t1 = time.perf_counter() - t0
     return {"value": npairs / t1, "unit": "pairs/s", "cores": nthr, "kind": "oracle",
-            "sample": f"DD(r, mu) of the first {n2} points of the catalogue ({npairs} pairs) in {t1:.1f} s"}
+            "sample": f"DD(r, mu) of the first {n2} points of the catalogue ({npairs} pairs) in {t1:.1f} s "
+                      f"on {nthr} threads ({src})",
+            "host": host_info()}
 
 
 def bench_xi(args):
@@ -279,6 +368,22 @@ def bench_ss(args):
     t_alm = (msN[2] + msR[2]) / max(nlN[2] + nlR[2], 1) / 1e3
     launches = (nlN[2] + nlR[2]) / args.steps
     achieved = pairs * flop_per_pair(lmax) / launches / t_alm
+    fp64 = None
+    if not args.no_fp64 and prec != T.PREC_FP64:
+        # the same step on the plain FP64 path: time and the accuracy of this precision
+        print("[bench] ss fp64 comparison", file=sys.stderr, flush=True)
+        hN = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+        hR = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+        step()  # the first step allocates the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z64 = step()
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        hN.close()
+        hR.close()
+        fp64 = {"ms_per_step": dt64 * 1e3, "speedup_vs_fp64": dt64 / dt,
+                "rel_err_vs_fp64_path": (z - z64).abs().max().item() / z64.abs().max().item()}
     line = {
         "metric": "pairs/s into a_lm(r), Szapudi-Szalay estimator with 50x explicit randoms, 1 GPU",
         "value": pairs / dt, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -293,7 +398,118 @@ def bench_ss(args):
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU, "traffic": None, "flop_per_pair": flop_per_pair(lmax),
                      "avg_launch_ms": t_alm * 1e3, "launches_per_step": launches},
+        "fp64_path": fp64,
         "cpu_baseline": None,
+        "build": build_info(),
+    }
+    print(json.dumps(line))
+
+
+def bench_c5(args):
+    """Large batched sweep with randoms: catalogues of N_D ~ logU[1e5, 4e5]
+    clustered points (Zel'dovich + RSD, sigma_Psi = 5, f = 0.8) each with 5 N_D
+    uniform randoms in a 1500 Mpc/h box, weights 1 and -N_D/N_R (the
+    data-minus-randoms numerator of eq. (ssest)), 12 bins over [10, 130],
+    lmax 10, every multipole with L <= 4. The full sweep is 512 catalogues;
+    a step times the first --ncat of them (16 by default) in one
+    tpcf_run_catalogs call, and catalogues/hour of the sweep is extrapolated
+    from it."""
+    import torch
+    from paper_2408_03036_amd import catalogs as C
+    from paper_2408_03036_amd import tpcf as T
+
+    box, sigma, fgrowth = 1500.0, 5.0, 0.8
+    edges = np.linspace(10.0, 130.0, 13)
+    lmax, Lmax = 10, 4
+    mults = all_multipoles(lmax, Lmax)
+    ncat_sweep = 512
+    ncat = min(args.ncat if args.ncat != 64 else 16, ncat_sweep)
+    nd_all = C.log_uniform_sizes(ncat_sweep, 100_000, 400_000, C.BASE_SEED + 555)
+    nd = nd_all[:ncat]
+    print(f"[bench] generating {ncat} of the {ncat_sweep} data + 5x randoms catalogues on the GPU",
+          file=sys.stderr, flush=True)
+    parts, wparts, sizes = [], [], []
+    for i, n in enumerate(nd):
+        D = C.zeldovich_torch(int(n), box, sigma, fgrowth, C.catalogue_seed(1000 + i), grid=256, device="cuda:0")
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(C.randoms_seed(1000 + i))
+        R = torch.rand((5 * int(n), 3), generator=g, device="cuda:0", dtype=torch.float64) * box
+        parts += [D, R]
+        wparts.append(torch.from_numpy(C.dr_weights(int(n), 5 * int(n))).cuda())
+        sizes.append(6 * int(n))
+    pos = torch.cat(parts, dim=0).contiguous()
+    w = torch.cat(wparts, dim=0).contiguous()
+    del parts, wparts
+    sizes = np.array(sizes, dtype=np.int64)
+    torch.cuda.synchronize()
+    prec_id = {"bf16x3": T.PREC_MIXED_BF16X3, "bf16x6": T.PREC_MIXED_BF16X6,
+               "fp32": T.PREC_FP32, "fp64": T.PREC_FP64}[args.precision]
+
+    def run(prec, steps, warmup):
+        h = T.Handle(box, edges, lmax, precision=prec, grid_refine=args.refine, workspace_limit=160 << 30)
+        h.set_timing(True)
+        for _ in range(warmup):
+            h.run_catalogs(sizes, nd, pos, w, mults)
+        h.sync()
+        h.stage_times()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = h.run_catalogs(sizes, nd, pos, w, mults)
+        h.sync()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ms, nl = h.stage_times()
+        npairs = h.pair_count()
+        h.close()
+        return dt, ms, nl, npairs, out
+
+    print(f"[bench] c5 {args.precision}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+    dt, ms, nl, npairs, out = run(prec_id, args.steps, args.warmup)
+    t_alm = ms[2] / max(nl[2], 1) / 1e3
+    launches = nl[2] / args.steps
+    achieved = npairs / launches * flop_per_pair(lmax) / t_alm
+    t_pair = (ms[1] + ms[2]) / args.steps / 1e3
+    roof = {"kernel": "k_pair_alm<float,10> (harmonic pass)", "bound": "alu",
+            "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": None, "flop_per_pair": flop_per_pair(lmax),
+            "avg_launch_ms": t_alm * 1e3, "launches_per_step": launches,
+            "pair_pass_frac": npairs * flop_per_pair(lmax) / t_pair / PEAK_FP32_VALU if t_pair > 0 else None}
+    stages = {k: ms[i] / args.steps for i, k in
+              enumerate(["grid_ms", "pair_bin_ms", "pair_alm_ms", "contract_ms", "finalize_ms"])}
+    fp64 = None
+    if not args.no_fp64 and prec_id != T.PREC_FP64:
+        print("[bench] c5 fp64 comparison", file=sys.stderr, flush=True)
+        dt64, ms64, nl64, np64, out64 = run(T.PREC_FP64, 1, 0)
+        err = (out - out64).abs().max().item() / out64.abs().max().item()
+        fp64 = {"value": np64 / dt64, "unit": "pairs/s", "ms_per_step": dt64 * 1e3,
+                "catalogs_per_hour": ncat * 3600.0 / dt64, "speedup_mixed_vs_fp64": dt64 / dt,
+                "mixed_rel_err_vs_fp64_path": err, "pairs_equal": int(np64) == int(npairs)}
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        n0 = int(sizes[0])
+        cpu = cpu_baseline(pos[:n0].cpu().numpy(), box, edges, lmax, w=w[:n0].cpu().numpy(),
+                           what="catalogue 0 (data + 5x randoms)")
+    # weights make the split-BF16 request run the six-product split
+    eff = {"bf16x3": "bf16x6"}.get(args.precision, args.precision)
+    line = {
+        "metric": METRIC, "value": npairs / dt, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec_id != T.PREC_FP64 else "f64", "data": "synthetic",
+        "config": {"workload": f"large batched sweep with randoms: {ncat} of {ncat_sweep} catalogues timed "
+                               f"(N_D log-uniform [1e5,4e5] Zel'dovich+RSD + 5 N_D randoms, weights 1 and "
+                               f"-N_D/N_R), 1500 Mpc/h boxes, 12 bins [10,130] Mpc/h, lmax 10, L<=4 "
+                               f"({len(mults)} multipoles)",
+                   "precision": args.precision, "precision_effective": eff, "ncat": int(ncat),
+                   "points": int(sizes.sum()), "pairs_per_step": int(npairs), "parallelism": "single GPU"},
+        "catalogs_per_hour": ncat * 3600.0 / dt,
+        "sweep_hours_extrapolated": ncat_sweep / (ncat * 3600.0 / dt),
+        "stages_ms": stages,
+        "roofline": roof,
+        "fp64_path": fp64,
+        "cpu_baseline": cpu,
+        "build": build_info(),
     }
     print(json.dumps(line))
 
@@ -382,8 +598,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--refine", type=int, default=0)
-    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov", "ss"],
+    ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov", "ss", "c5"],
                     help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF; "
+                         "c5: data + 5x randoms catalogues of the large sweep (a timed subset); "
                          "cov: covariance and precision over mock data vectors; "
                          "ss: Szapudi-Szalay estimator with 50x explicit randoms, edge-corrected")
     ap.add_argument("--isotropic", action="store_true",
@@ -402,6 +619,9 @@ def main():
         return
     if args.workload == "ss":
         bench_ss(args)
+        return
+    if args.workload == "c5":
+        bench_c5(args)
         return
 
     import torch
@@ -448,6 +668,19 @@ def main():
             "frac": achieved / PEAK_FP32_VALU, "traffic": traffic,
             "flop_per_pair": flop_per_pair(lmax), "avg_launch_ms": t_alm * 1e3,
             "launches_per_step": launches_per_step}
+    # the whole pair pass (binning + harmonics), algorithmic F(lmax) per pair
+    t_pair = (ms[1] + ms[2]) / args.steps / 1e3
+    if t_pair > 0:
+        roof["pair_pass_frac"] = npairs * flop_per_pair(lmax) / t_pair / PEAK_FP32_VALU
+        roof["pair_pass_ms"] = t_pair * 1e3
+    if args.ncat == 64 and prec_id != T.PREC_FP64 and not args.isotropic:
+        ex = executed_flop(["paper_2408_03036_amd/csrc/tpcf_pairs.hip",
+                            "paper_2408_03036_amd/csrc/tpcf_internal.h",
+                            "paper_2408_03036_amd/csrc/tpcf.cpp"])
+        if ex is not None:
+            roof["executed_flop_per_pair"] = ex["per_pair"]
+            roof["executed_frac"] = npairs / launches_per_step * ex["per_pair"] / t_alm / PEAK_FP32_VALU
+            roof["executed_source"] = ex["summary"]
     stages = {"grid_ms": ms[0] / args.steps, "pair_bin_ms": ms[1] / args.steps,
               "pair_alm_ms": ms[2] / args.steps, "contract_ms": ms[3] / args.steps,
               "finalize_ms": ms[4] / args.steps}
@@ -457,8 +690,11 @@ def main():
                    "tflops_fp32_equiv": cflop / (stages["contract_ms"] / 1e3) / 1e12
                    if stages["contract_ms"] > 0 else None,
                    "mfma_products_per_fp32_product": mfma_mult}
+    nflop = needed_contraction_flop(sizes, len(edges) - 1, lmax, Lmax)
+    contraction["needed_flop"] = nflop
     if prec_id in (T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6) and stages["contract_ms"] > 0:
         contraction["frac_bf16_peak"] = cflop * mfma_mult / (stages["contract_ms"] / 1e3) / PEAK_BF16_MFMA
+        contraction["needed_frac_bf16_peak"] = nflop * mfma_mult / (stages["contract_ms"] / 1e3) / PEAK_BF16_MFMA
     if args.isotropic:
         # only the l1 = l2 blocks, on FP64 MFMA: sum over catalogues, (l, m) and parts of 2 P nb^2
         nb = len(edges) - 1
@@ -512,6 +748,7 @@ def main():
         "contraction": contraction,
         "fp64_path": fp64,
         "cpu_baseline": cpu,
+        "build": build_info(),
     }
     print(json.dumps(line))
 
