@@ -90,6 +90,15 @@ def make_batch(torch, ncat, lo, hi, box, sigma, f, grid, device):
     return sizes, pos
 
 
+def tune(h, sizes, pos, w, n_data, args):
+    """Launch plan for the handle, tuned on the whole batch (outside the timed
+    steps), or read from --plan-cache; None with --no-tune or a fixed --refine."""
+    if args.no_tune or args.refine:
+        return None
+    print(f"[bench] tuning the plan on the batch ({len(sizes)} catalogues)", file=sys.stderr, flush=True)
+    return h.autotune_plan(pos, w, sizes=sizes, n_data=n_data, cache=args.plan_cache)
+
+
 def time_steps(torch, h, sizes, pos, mults, steps, warmup):
     for _ in range(warmup):
         h.run_catalogs(sizes, sizes, pos, None, mults)
@@ -342,6 +351,8 @@ def bench_ss(args):
     # the neighbour lists of 1e5 randoms per primary need room: 200 GiB of the 288 GB
     hN = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
     hR = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+    plans = {"data_minus_randoms": tune(hN, np.array([nd + nr]), pos, w, [nd], args),
+             "randoms": tune(hR, np.array([nr]), Rp, None, [nr], args)}
     hN.set_timing(True)
     hR.set_timing(True)
 
@@ -374,6 +385,8 @@ def bench_ss(args):
         print("[bench] ss fp64 comparison", file=sys.stderr, flush=True)
         hN = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
         hR = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+        tune(hN, np.array([nd + nr]), pos, w, [nd], args)
+        tune(hR, np.array([nr]), Rp, None, [nr], args)
         step()  # the first step allocates the workspace
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -399,6 +412,7 @@ def bench_ss(args):
                      "frac": achieved / PEAK_FP32_VALU, "traffic": None, "flop_per_pair": flop_per_pair(lmax),
                      "avg_launch_ms": t_alm * 1e3, "launches_per_step": launches},
         "fp64_path": fp64,
+        "plan": plans,
         "cpu_baseline": None,
         "build": build_info(),
     }
@@ -445,8 +459,11 @@ def bench_c5(args):
     prec_id = {"bf16x3": T.PREC_MIXED_BF16X3, "bf16x6": T.PREC_MIXED_BF16X6,
                "fp32": T.PREC_FP32, "fp64": T.PREC_FP64}[args.precision]
 
+    plans = {}
+
     def run(prec, steps, warmup):
         h = T.Handle(box, edges, lmax, precision=prec, grid_refine=args.refine, workspace_limit=160 << 30)
+        plans[prec] = tune(h, sizes, pos, w, nd, args)
         h.set_timing(True)
         for _ in range(warmup):
             h.run_catalogs(sizes, nd, pos, w, mults)
@@ -484,7 +501,8 @@ def bench_c5(args):
         err = (out - out64).abs().max().item() / out64.abs().max().item()
         fp64 = {"value": np64 / dt64, "unit": "pairs/s", "ms_per_step": dt64 * 1e3,
                 "catalogs_per_hour": ncat * 3600.0 / dt64, "speedup_mixed_vs_fp64": dt64 / dt,
-                "mixed_rel_err_vs_fp64_path": err, "pairs_equal": int(np64) == int(npairs)}
+                "mixed_rel_err_vs_fp64_path": err, "pairs_equal": int(np64) == int(npairs),
+                "plan": plans.get(T.PREC_FP64)}
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -505,6 +523,7 @@ def bench_c5(args):
                    "points": int(sizes.sum()), "pairs_per_step": int(npairs), "parallelism": "single GPU"},
         "catalogs_per_hour": ncat * 3600.0 / dt,
         "sweep_hours_extrapolated": ncat_sweep / (ncat * 3600.0 / dt),
+        "plan": plans.get(prec_id),
         "stages_ms": stages,
         "roofline": roof,
         "fp64_path": fp64,
@@ -597,7 +616,9 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "fp32", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--refine", type=int, default=0)
+    ap.add_argument("--refine", type=int, default=0, help="fixed grid refinement (no plan tuning)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan")
+    ap.add_argument("--plan-cache", default=None, help="JSON plan cache to read and extend")
     ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov", "ss", "c5"],
                     help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF; "
                          "c5: data + 5x randoms catalogues of the large sweep (a timed subset); "
@@ -646,6 +667,7 @@ def main():
           file=sys.stderr, flush=True)
     h = T.Handle(box, edges, lmax, precision=prec_id, flags=flags, grid_refine=args.refine,
                  workspace_limit=96 << 30)
+    plan = tune(h, sizes, pos, None, sizes, args)
     h.set_timing(True)
     dt, ms, nl, npairs, out = time_steps(torch, h, sizes, pos, mults, args.steps, args.warmup)
     rebinned = h.rebinned_count() / max(args.steps + args.warmup, 1)
@@ -710,6 +732,7 @@ def main():
         print("[bench] fp64 comparison", file=sys.stderr, flush=True)
         h = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=flags, grid_refine=args.refine,
                      workspace_limit=96 << 30)
+        plan64 = tune(h, sizes, pos, None, sizes, args)
         h.set_timing(True)
         dt64, ms64, nl64, np64, out64 = time_steps(torch, h, sizes, pos, mults, max(2, args.steps // 2), 1)
         h.close()
@@ -720,7 +743,7 @@ def main():
                 "pair_alm_ms": ms64[2] / max(2, args.steps // 2),
                 "contract_ms": ms64[3] / max(2, args.steps // 2),
                 "speedup_mixed_vs_fp64": dt64 / dt,
-                "mixed_rel_err_vs_fp64_path": err, "pairs_equal": int(np64) == int(npairs)}
+                "mixed_rel_err_vs_fp64_path": err, "pairs_equal": int(np64) == int(npairs), "plan": plan64}
 
     cpu = None
     if not args.no_cpu:
@@ -742,6 +765,7 @@ def main():
                    "precision": args.precision, "ncat": args.ncat, "points": ntot,
                    "pairs_per_step": int(npairs), "parallelism": "single GPU"},
         "catalogs_per_hour": cats_per_hour,
+        "plan": plan,
         "stages_ms": stages,
         "rebinned_primaries_per_step": rebinned,
         "roofline": roof,

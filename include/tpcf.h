@@ -225,6 +225,50 @@ tpcf_status tpcf_autotune(tpcf_handle h, const double* d_pos, const double* d_w,
                           int32_t nmu, int32_t* h_refine, double* h_ms);
 
 /*
+ * Launch plan of the estimator, chosen by tpcf_autotune_plan or set by the
+ * caller (for example from a cache of plans keyed by device, precision, lmax,
+ * bins and catalogue density). Results do not depend on the refinement (every
+ * bin decision is exact); the list mode and the contraction step change only
+ * the order of FP32 sums.
+ *  grid_refine:   cells per r_max along an axis, 1 .. 4; 0 = automatic.
+ *  list_mode:     harmonic pass: 0 one lane per (primary, bin) list, 1 one
+ *                 wavefront per list (FP32 paths with lmax <= 6; elsewhere
+ *                 the lane kernel runs), -1 = by the predicted list length.
+ *  contract_step: primaries per step of the split-BF16 contraction: 16, 32,
+ *                 64 or 128 (the longest that fits when that is shorter), or
+ *                 0 = the longest that fits. Other precisions ignore it.
+ *  ms:            (tpcf_autotune_plan) the timed pair pass and contraction of
+ *                 the sample with this plan, in ms.
+ */
+typedef struct {
+    int32_t grid_refine;
+    int32_t list_mode;
+    int32_t contract_step;
+    int32_t reserved;
+    double ms;
+} tpcf_plan;
+
+/*
+ * Times steps 1-3 (grid build, pair pass, contraction) of a sample batch
+ * (ncat, h_n, h_n_data, d_pos, d_w as for tpcf_run_catalogs; for example the
+ * batch itself, or one representative catalogue) with every admissible grid
+ * refinement, both list modes where the wavefront kernel exists, and for the
+ * non-isotropic split-BF16 precisions the longest contraction step and 64;
+ * keeps the fastest plan on the handle and returns it.
+ *  h_ms: NULL, or 16 entries receiving the time (ms) of each candidate at
+ *        [((grid_refine - 1) * 2 + list_mode) * 2 + (contract_step ? 1 : 0)],
+ *        -1 where it was not run (or its lists did not fit the workspace).
+ * The sample's grid and sums are not kept: build or run afterwards.
+ */
+tpcf_status tpcf_autotune_plan(tpcf_handle h, int32_t ncat, const int64_t* h_n, const int64_t* h_n_data,
+                               const double* d_pos, const double* d_w, tpcf_plan* h_plan, double* h_ms);
+/* Applies a plan (out-of-range fields give TPCF_ERR_RANGE); it takes effect
+ * from the next tpcf_build_grid or tpcf_run_catalogs. */
+tpcf_status tpcf_set_plan(tpcf_handle h, const tpcf_plan* h_plan);
+/* The handle's current plan (ms = 0). */
+tpcf_status tpcf_get_plan(tpcf_handle h, tpcf_plan* h_plan);
+
+/*
  * Szapudi-Szalay estimator with explicit randoms (eq. (ssest)), isotropic
  * multipoles: edge correction by the random triplet counts. With N_l the
  * multipoles (l, l, 0) of a data-minus-randoms run (weights 1 and -N_D/N_R,

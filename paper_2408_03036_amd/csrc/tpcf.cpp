@@ -28,6 +28,7 @@ using namespace tpcf;
 namespace {
 
 constexpr int kStages = 6;                // timed stages (tpcf_stage_times)
+constexpr int kPlanCandidates = 16;       // refinement x list mode x contraction step
 const double kPi = 3.14159265358979323846;
 
 struct DevBuf {
@@ -57,6 +58,8 @@ struct tpcf_handle_s {
     std::string err;
     int nb = 0, lmax = 0, NV = 0, mode = 0, fp64 = 0;
     int refine = 0;
+    int list_mode = -1;    // harmonic pass: -1 by predicted list length, 0 a lane per list, 1 a wavefront per list
+    int contract_step = 0; // split-BF16 contraction step (primaries), 0 = the longest that fits
     int64_t limit = 0;
     int64_t used = 0;
     std::vector<DevBuf*> bufs;
@@ -614,8 +617,9 @@ tpcf_status plan_chunks(tpcf_handle h) {
     int64_t budget = h->limit / 2;
     int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
     cap = std::min<int64_t>(cap, 1 << 21);
-    // list offsets are 32-bit: keep a chunk's predicted room within 3.5e9 entries
-    cap = std::min<int64_t>(cap, (int64_t)(3.5e9 / hits_room));
+    // list offsets are 32-bit: keep a chunk's predicted room within 3.2e9
+    // entries, so that the 256 list regions get 15 % of slack within 4e9
+    cap = std::min<int64_t>(cap, (int64_t)(3.2e9 / hits_room));
     cap = std::max<int64_t>(h->kc, cap / h->kc * h->kc);
     h->chunk_cap = cap;
     h->sub_start.clear();
@@ -661,7 +665,9 @@ tpcf_status plan_chunks(tpcf_handle h) {
         }
     }
     h->ldA = (maxch + 63) / 64 * 64;
-    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, (double)maxch * hits_room));
+    // 15 % above the predicted room: a catalogue of even density fills its
+    // regions to their prediction on average, and the 256 regions differ
+    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, 1.15 * (double)maxch * hits_room));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
@@ -784,7 +790,9 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     a.unit_w = h->unit_w ? 1 : 0;
     // a wavefront per list once lists average 256 records or more (the
     // predicted hits of a primary of the densest catalogue, over the bins)
-    a.wave_per_list = (!h->fp64 && h->lmax <= 6 && h->hits_per_list >= 256.0) ? 1 : 0;
+    // (or as the plan sets it)
+    const bool wave_ok = !h->fp64 && h->lmax <= 6;
+    a.wave_per_list = (wave_ok && (h->list_mode == 1 || (h->list_mode < 0 && h->hits_per_list >= 256.0))) ? 1 : 0;
     a.self_lo = h->self_lo ? 1 : 0;
     a.boff = P<uint32_t>(h->d_boff);
     a.cnt = P<uint32_t>(h->d_cnt);
@@ -821,6 +829,7 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     c.mode = (h->mode == TPCF_PREC_MIXED_BF16X3 && !h->unit_w) ? TPCF_PREC_MIXED_BF16X6 : h->mode;
     c.unit_weights = h->unit_w ? 1 : 0;
     c.pw = P<float>(h->d_pw);
+    c.ks_max = h->contract_step;
     if (h->cfg.flags & TPCF_F_ISOTROPIC) {
         // only the l1 = l2 blocks are formed; the rest of the partials is zero
         HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(P<double>(h->d_part) + (int64_t)ch.sub_begin * h->gsize),
@@ -1014,6 +1023,46 @@ tpcf_status validate_config(const tpcf_config* c) {
     if (mode == TPCF_PREC_MIXED_BF16X3 &&
         contract_lds_bytes(TPCF_PREC_MIXED_BF16X6, c->nbins, c->lmax) > 160 * 1024)
         return TPCF_ERR_RANGE;
+    return TPCF_OK;
+}
+
+// Steps 1-3 (and with d_out step 4) of ncat catalogues, in groups of whole
+// catalogues whose points fit a quarter of the workspace. self_lo: every
+// multipole asked for has L <= lmax.
+tpcf_status run_groups(tpcf_handle h, int32_t ncat, const int64_t* h_n, const int64_t* h_n_data,
+                       const double* d_pos, const double* d_w, bool self_lo, int32_t n_mult,
+                       const int32_t* h_l1l2L, double* d_out) {
+    tpcf_status st;
+    const int64_t per_point = 96;
+    const int64_t max_pts = std::max<int64_t>(1, std::min<int64_t>((h->limit / 4) / per_point, (1LL << 31) - 1));
+    int c0 = 0;
+    int64_t pos_off = 0;
+    const int64_t per_out = (int64_t)n_mult * h->nb * h->nb;
+    while (c0 < ncat) {
+        int c1 = c0;
+        int64_t pts = 0;
+        while (c1 < ncat && (c1 == c0 || pts + h_n[c1] <= max_pts)) pts += h_n[c1++];
+        std::vector<int64_t> n(h_n + c0, h_n + c1), nd(h_n_data + c0, h_n_data + c1);
+        h->stage = 0;
+        if ((st = build_grid_group(h, d_pos + 3 * pos_off, d_w ? d_w + pos_off : nullptr, n, nd)) != TPCF_OK)
+            return st;
+        if ((st = check_nonfinite(h)) != TPCF_OK) return st;
+        if ((st = plan_chunks(h)) != TPCF_OK) return st;
+        // The self moments of order above lmax cancel from every multipole
+        // of L <= lmax (their coefficients sum to zero over m), and this run
+        // keeps no per-m sums: the harmonic pass may stop them at lmax.
+        h->self_lo = self_lo;
+        h->self_cut = h->self_lo;
+        st = pair_pass(h, true);
+        h->self_lo = false;
+        if (st != TPCF_OK) return st;
+        if ((st = reduce_group(h)) != TPCF_OK) return st;
+        h->stage = 3;
+        if (d_out && (st = finalize_group(h, n_mult, h_l1l2L, d_out + per_out * c0)) != TPCF_OK) return st;
+        pos_off += pts;
+        c0 = c1;
+    }
+    h->alm_kept = false;
     return TPCF_OK;
 }
 
@@ -1211,38 +1260,7 @@ tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n, c
         if (h_n_data[c] < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
     }
     HIPCHK(hipSetDevice(h->device));
-    // groups of whole catalogues whose points fit a quarter of the workspace
-    const int64_t per_point = 96;
-    const int64_t max_pts = std::max<int64_t>(1, std::min<int64_t>((h->limit / 4) / per_point, (1LL << 31) - 1));
-    int c0 = 0;
-    int64_t pos_off = 0;
-    const int64_t per_out = (int64_t)n_mult * h->nb * h->nb;
-    while (c0 < ncat) {
-        int c1 = c0;
-        int64_t pts = 0;
-        while (c1 < ncat && (c1 == c0 || pts + h_n[c1] <= max_pts)) pts += h_n[c1++];
-        std::vector<int64_t> n(h_n + c0, h_n + c1), nd(h_n_data + c0, h_n_data + c1);
-        h->stage = 0;
-        if ((st = build_grid_group(h, d_pos + 3 * pos_off, d_w ? d_w + pos_off : nullptr, n, nd)) != TPCF_OK)
-            return st;
-        if ((st = check_nonfinite(h)) != TPCF_OK) return st;
-        if ((st = plan_chunks(h)) != TPCF_OK) return st;
-        // The self moments of order above lmax cancel from every multipole
-        // of L <= lmax (their coefficients sum to zero over m), and this run
-        // keeps no per-m sums: the harmonic pass may stop them at lmax.
-        h->self_lo = max_L <= h->lmax;
-        h->self_cut = h->self_lo;
-        st = pair_pass(h, true);
-        h->self_lo = false;
-        if (st != TPCF_OK) return st;
-        if ((st = reduce_group(h)) != TPCF_OK) return st;
-        h->stage = 3;
-        if ((st = finalize_group(h, n_mult, h_l1l2L, d_out + per_out * c0)) != TPCF_OK) return st;
-        pos_off += pts;
-        c0 = c1;
-    }
-    h->alm_kept = false;
-    return TPCF_OK;
+    return run_groups(h, ncat, h_n, h_n_data, d_pos, d_w, max_L <= h->lmax, n_mult, h_l1l2L, d_out);
 }
 
 tpcf_status tpcf_xi_count(tpcf_handle h, int32_t nmu, int64_t* d_counts) {
@@ -1530,7 +1548,6 @@ tpcf_status tpcf_autotune(tpcf_handle h, const double* d_pos, const double* d_w,
             best = h->g.single ? k : h->g.k;
             best_ms = ms;
         }
-        if (h->g.single) break;  // every refinement gives the one-cell grid
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1544,6 +1561,125 @@ tpcf_status tpcf_autotune(tpcf_handle h, const double* d_pos, const double* d_w,
     }
     h->refine = best;
     *h_refine = best;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_set_plan(tpcf_handle h, const tpcf_plan* p) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!p) return fail(h, TPCF_ERR_ARG, "NULL plan");
+    if (p->grid_refine < 0 || p->grid_refine > 4) return fail(h, TPCF_ERR_RANGE, "grid_refine must be in 0 .. 4");
+    if (p->list_mode < -1 || p->list_mode > 1) return fail(h, TPCF_ERR_RANGE, "list_mode must be -1, 0 or 1");
+    if (p->contract_step != 0 && p->contract_step != 16 && p->contract_step != 32 && p->contract_step != 64 &&
+        p->contract_step != 128)
+        return fail(h, TPCF_ERR_RANGE, "contract_step must be 0, 16, 32, 64 or 128");
+    h->refine = p->grid_refine;
+    h->list_mode = p->list_mode;
+    h->contract_step = p->contract_step;
+    h->stage = 0;  // a new plan applies from the next grid build
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_get_plan(tpcf_handle h, tpcf_plan* p) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!p) return fail(h, TPCF_ERR_ARG, "NULL plan");
+    p->grid_refine = h->refine;
+    p->list_mode = h->list_mode;
+    p->contract_step = h->contract_step;
+    p->reserved = 0;
+    p->ms = 0.0;
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_autotune_plan(tpcf_handle h, int32_t ncat, const int64_t* h_n, const int64_t* h_n_data,
+                               const double* d_pos, const double* d_w, tpcf_plan* h_plan, double* h_ms) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (ncat < 1 || !h_n || !h_n_data || !d_pos || !h_plan)
+        return fail(h, TPCF_ERR_ARG, "ncat >= 1 and non-NULL h_n, h_n_data, d_pos, h_plan required");
+    for (int c = 0; c < ncat; ++c) {
+        if (h_n[c] < 1 || h_n[c] > (1LL << 27)) return fail(h, TPCF_ERR_ARG, "catalogue size out of range");
+        if (h_n_data[c] < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
+    }
+    HIPCHK(hipSetDevice(h->device));
+    if (h_ms)
+        for (int i = 0; i < kPlanCandidates; ++i) h_ms[i] = -1.0;
+    const bool timing = h->timing;
+    h->timing = false;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // the candidates: every admissible refinement; both list modes where the
+    // wavefront kernel exists (FP32, lmax <= 6); for the split-BF16
+    // contraction (not the isotropic one) the longest step and 64
+    const bool wave_ok = !h->fp64 && h->lmax <= 6;
+    const bool bf = (h->mode == TPCF_PREC_MIXED_BF16X3 || h->mode == TPCF_PREC_MIXED_BF16X6) &&
+                    !(h->cfg.flags & TPCF_F_ISOTROPIC);
+    const int steps[2] = {0, 64};
+    tpcf_plan best{};
+    best.ms = -1.0;
+    tpcf_status st = TPCF_OK;
+    int last_k = -1;
+    for (int k = 1; k <= 4 && st == TPCF_OK; ++k) {
+        // admissibility from the grid the first catalogue gets (a refinement
+        // that does not fit falls back to a coarser one, or the one-cell grid)
+        h->refine = k;
+        h->stage = 0;
+        if ((st = build_grid_group(h, d_pos, d_w, {h_n[0]}, {h_n_data[0]})) != TPCF_OK) break;
+        if (h->g.k == last_k || (h->g.k != k && !h->g.single)) continue;
+        last_k = h->g.k;
+        for (int mode = 0; mode <= (wave_ok ? 1 : 0) && st == TPCF_OK; ++mode)
+            for (int si = 0; si <= (bf ? 1 : 0) && st == TPCF_OK; ++si) {
+                h->list_mode = mode;
+                h->contract_step = steps[si];
+                double ms = 0.0;
+                // one untimed pass, then the timed one: grid build, pair pass, contraction
+                bool fits = true;
+                for (int rep = 0; rep < 2 && st == TPCF_OK; ++rep) {
+                    if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(h, TPCF_ERR_DEVICE, "hipEventRecord"); break; }
+                    if ((st = run_groups(h, ncat, h_n, h_n_data, d_pos, d_w, true, 0, nullptr, nullptr)) != TPCF_OK) {
+                        // a candidate whose lists do not fit the workspace is not admissible
+                        if (st == TPCF_ERR_ALLOC) {
+                            HIPCHK(hipStreamSynchronize(h->stream));
+                            st = TPCF_OK;
+                            fits = false;
+                        }
+                        break;
+                    }
+                    if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        st = fail(h, TPCF_ERR_DEVICE, "hipEvent");
+                        break;
+                    }
+                    float f = 0.f;
+                    hipEventElapsedTime(&f, e0, e1);
+                    ms = f;
+                }
+                if (st != TPCF_OK) break;
+                if (!fits) continue;
+                if (h_ms) h_ms[((k - 1) * 2 + mode) * 2 + si] = ms;
+                if (best.ms < 0.0 || ms < best.ms) {
+                    best.grid_refine = h->g.single ? k : h->g.k;
+                    best.list_mode = mode;
+                    best.contract_step = steps[si];
+                    best.ms = ms;
+                }
+            }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    h->timing = timing;
+    h->stage = 0;  // the sample's grid and sums are not kept
+    h->self_cut = false;
+    h->pairs_valid = false;
+    if (st == TPCF_OK && best.ms < 0.0) st = fail(h, TPCF_ERR_ALLOC, "no plan fits the workspace");
+    if (st != TPCF_OK) {
+        h->refine = h->cfg.grid_refine;
+        h->list_mode = -1;
+        h->contract_step = 0;
+        return st;
+    }
+    h->refine = best.grid_refine;
+    h->list_mode = best.list_mode;
+    h->contract_step = best.contract_step;
+    *h_plan = best;
     return TPCF_OK;
 }
 

@@ -1104,14 +1104,15 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
 }  // namespace
 
 // Step length and buffer count of the split-BF16 contraction: the longest
-// step (64, 32 or 16 primaries) whose staging fits the per-thread registers,
-// double-buffered when both buffers fit in LDS.
+// step (128, 64, 32 or 16 primaries, at most ks_max when given) whose staging
+// fits the per-thread registers, double-buffered when both buffers fit in LDS.
 struct BfPlan { int KS, nbuf; size_t lds; };
-BfPlan bf_plan(int npc, int ncol, bool weighted) {
+BfPlan bf_plan(int npc, int ncol, bool weighted, int ks_max = 0) {
     const int nplanes = weighted ? 2 * npc : npc;
     const int ipt = weighted ? bf_ipt<true>() : bf_ipt<false>();
+    const int top = ks_max >= 16 ? std::min(ks_max, 128) : 128;
     for (int nbuf = 2; nbuf >= 1; --nbuf)
-        for (int KS = 128; KS >= 16; KS /= 2) {
+        for (int KS = top; KS >= 16; KS /= 2) {
             if ((size_t)ncol * (KS / 8) > (size_t)64 * kBfWaves * ipt) continue;
             const size_t lds = (size_t)nbuf * nplanes * ncol * (KS + 8) * sizeof(uint16_t);
             if (lds <= 160 * 1024) return {KS, nbuf, lds};
@@ -1125,7 +1126,7 @@ hipError_t launch_contract_bf16_w(const ContractArgs& a, hipStream_t s) {
     const int nt0 = (K0 + 31) / 32;
     const int ntiles0 = nt0 * (nt0 + 1) / 2;
     const int ngroups = (ntiles0 + kBfWaves * kBfTPW - 1) / (kBfWaves * kBfTPW);
-    const BfPlan pl = bf_plan(NPC, nt0 * 32, !a.unit_weights);
+    const BfPlan pl = bf_plan(NPC, nt0 * 32, !a.unit_weights, a.ks_max);
     if (pl.KS == 0) return hipErrorInvalidValue;
     const hipError_t e = allow_full_lds((const void*)k_contract_bf16<NPC, W>);
     if (e != hipSuccess) return e;

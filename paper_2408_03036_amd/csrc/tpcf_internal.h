@@ -221,6 +221,7 @@ struct ContractArgs {
     int mode;                // 0 fp64, 1 fp32, 2 bf16x3, 3 bf16x6
     int unit_weights;        // all weights 1: skip the weight multiply
     const float* pw;         // FP32 weights, sorted order (split-BF16 modes)
+    int ks_max;              // split-BF16: longest step in primaries (0: the longest that fits)
 };
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s);
 // Isotropic schedule: only the l1 = l2 blocks of every G_m (nb <= 32); the

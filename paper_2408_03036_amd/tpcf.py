@@ -39,7 +39,7 @@ EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
            "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles", "tpcf_triangle_index",
            "tpcf_covariance", "tpcf_covariance_noalloc", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic", "tpcf_edge_correct",
-           "tpcf_autotune"]
+           "tpcf_autotune", "tpcf_autotune_plan", "tpcf_set_plan", "tpcf_get_plan"]
 
 
 class TpcfError(RuntimeError):
@@ -53,6 +53,15 @@ class Config(ctypes.Structure):
                 ("h_edges", ctypes.POINTER(ctypes.c_double)), ("lmax", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("grid_refine", ctypes.c_int32), ("workspace_limit", ctypes.c_int64)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("grid_refine", ctypes.c_int32), ("list_mode", ctypes.c_int32),
+                ("contract_step", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"grid_refine": self.grid_refine, "list_mode": self.list_mode,
+                "contract_step": self.contract_step, "ms": self.ms}
 
 
 _lib = None
@@ -116,6 +125,12 @@ def load():
     lib.tpcf_edge_correct.restype = st
     lib.tpcf_autotune.argtypes = [vp, vp, vp, i64, i64, i32, ctypes.POINTER(i32), vp]
     lib.tpcf_autotune.restype = st
+    lib.tpcf_autotune_plan.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.POINTER(Plan), vp]
+    lib.tpcf_autotune_plan.restype = st
+    lib.tpcf_set_plan.argtypes = [vp, ctypes.POINTER(Plan)]
+    lib.tpcf_set_plan.restype = st
+    lib.tpcf_get_plan.argtypes = [vp, ctypes.POINTER(Plan)]
+    lib.tpcf_get_plan.restype = st
     _lib = lib
     return lib
 
@@ -152,6 +167,8 @@ class Handle:
         self.nbins = self.edges.shape[0] - 1
         self.lmax = int(lmax)
         self.box = float(box)
+        self.precision = int(precision)
+        self.flags = int(flags)
         self.device = int(device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -202,6 +219,69 @@ class Handle:
         self._chk(self.lib.tpcf_autotune(self.h, _ptr(pos), _ptr(w), n, n if n_data is None else int(n_data),
                                          int(nmu), ctypes.byref(k), ctypes.c_void_p(ms.ctypes.data)))
         return int(k.value), ms
+
+    def plan_key(self, sizes):
+        """Key of a plan cache entry: the device's architecture, the handle's
+        precision, flags, bins, lmax and box, and the sample's number of
+        catalogues, mean size and mean density (points per r_max^3) in
+        factor-of-two buckets."""
+        import hashlib
+        import math
+        import torch
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        sizes = np.asarray(sizes, dtype=np.float64)
+        mean = float(sizes.mean())
+        dens = mean / self.box ** 3 * float(self.edges[-1]) ** 3
+        eh = hashlib.sha1(self.edges.tobytes()).hexdigest()[:10]
+        b = lambda x: int(round(math.log2(max(x, 1e-9))))
+        return (f"{arch}|prec{self.precision}|flags{self.flags}|lmax{self.lmax}|nb{self.nbins}|edges{eh}|"
+                f"box{self.box:g}|ncat2^{b(len(sizes))}|n2^{b(mean)}|nr3_2^{b(dens)}")
+
+    def autotune_plan(self, pos, w=None, sizes=None, n_data=None, cache=None):
+        """Chooses the launch plan (grid refinement, list mode, contraction
+        step) by timing steps 1-3 of the sample (one catalogue, or a batch
+        given by `sizes` as for run_catalogs), or takes it from the JSON plan
+        cache at `cache` when it holds this key; returns the plan as a dict
+        with the time of every candidate (ms, -1 where not run)."""
+        import json
+        import torch
+        _check_dev(pos, torch.float64, "pos")
+        _check_dev(w, torch.float64, "w")
+        sizes = np.ascontiguousarray(np.asarray([pos.shape[0]] if sizes is None else sizes, dtype=np.int64))
+        nd = np.ascontiguousarray(np.asarray(sizes if n_data is None else n_data, dtype=np.int64).reshape(-1))
+        key = self.plan_key(sizes)
+        entries = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                entries = json.load(f)
+            if key in entries:
+                e = entries[key]
+                plan = Plan(int(e["grid_refine"]), int(e["list_mode"]), int(e["contract_step"]), 0, 0.0)
+                self._chk(self.lib.tpcf_set_plan(self.h, ctypes.byref(plan)))
+                return dict(e, cached=True)
+        plan = Plan()
+        ms = np.full(16, -1.0)
+        self._chk(self.lib.tpcf_autotune_plan(self.h, sizes.shape[0], ctypes.c_void_p(sizes.ctypes.data),
+                                              ctypes.c_void_p(nd.ctypes.data), _ptr(pos), _ptr(w),
+                                              ctypes.byref(plan), ctypes.c_void_p(ms.ctypes.data)))
+        out = plan.as_dict()
+        out["candidates_ms"] = [round(float(v), 3) for v in ms]
+        if cache:
+            entries[key] = out
+            tmp = cache + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as f:
+                json.dump(entries, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(out, cached=False)
+
+    def set_plan(self, grid_refine=0, list_mode=-1, contract_step=0):
+        plan = Plan(int(grid_refine), int(list_mode), int(contract_step), 0, 0.0)
+        self._chk(self.lib.tpcf_set_plan(self.h, ctypes.byref(plan)))
+
+    def get_plan(self):
+        plan = Plan()
+        self._chk(self.lib.tpcf_get_plan(self.h, ctypes.byref(plan)))
+        return plan.as_dict()
 
     def alm_accumulate(self):
         self._chk(self.lib.tpcf_alm_accumulate(self.h))

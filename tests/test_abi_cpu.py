@@ -129,6 +129,9 @@ def test_host_helpers_match_oracle(lib):
     assert lib.tpcf_covariance_noalloc(None, 10, 10, None, 5, None, None, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_precision_matrix(None, 5, None, 10, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_autotune(None, None, None, 10, 10, 0, None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_autotune_plan(None, 1, None, None, None, None, None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_set_plan(None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_get_plan(None, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_edge_correct_isotropic(None, 3, None, None, None) == T.TPCF_ERR_ARG
 
 

@@ -489,6 +489,56 @@ def test_autotune_keeps_results(torch, dense_case):
     assert np.array_equal(dd, O.xi_counts(pos, 400.0, np.linspace(0.0, 60.0, 13), 40))
 
 
+def test_autotune_plan_keeps_results(torch, tmp_path):
+    """The plan autotuner times refinements, list modes and contraction steps
+    on a sample and keeps the fastest; the plan cache returns it without
+    timing. Across every plan, lmax = 0 triplet counts are bit-exact (the pair
+    set does not depend on the plan) and the lmax = 4 multipoles of the FP32
+    pair pass stay within the FP32 tolerance of the oracle."""
+    box, edges = 120.0, np.linspace(5.0, 30.0, 6)
+    pos = C.zeldovich(4000, box, 3.0, 0.8, 112, grid=32)
+    P = gpu(torch, pos)
+    ref0, _, res = O.run(pos, box, edges, 0, [(0, 0, 0)])
+    mults = O.all_multipoles(4, 2)
+    ref4, _, _ = O.run(pos, box, edges, 4, mults)
+    cache = str(tmp_path / "plans.json")
+    for prec in (T.PREC_FP32, T.PREC_MIXED_BF16X6):
+        h = T.Handle(box, edges, 4, precision=prec)
+        plan = h.autotune_plan(P, cache=cache)
+        say(f"  {PNAME[prec]}: tuned plan {plan}")
+        assert not plan["cached"] and plan["ms"] > 0
+        assert 1 <= plan["grid_refine"] <= 4 and plan["list_mode"] in (0, 1)
+        cur = h.get_plan()
+        assert (cur["grid_refine"], cur["list_mode"], cur["contract_step"]) == \
+            (plan["grid_refine"], plan["list_mode"], plan["contract_step"])
+        again = h.autotune_plan(P, cache=cache)
+        assert again["cached"] and again["grid_refine"] == plan["grid_refine"]
+        assert again["list_mode"] == plan["list_mode"] and again["contract_step"] == plan["contract_step"]
+        h.close()
+        for k in (1, 2, 3):
+            for mode in (0, 1):
+                for step in (0, 32):
+                    h0 = T.Handle(box, edges, 0, precision=prec)
+                    h0.set_plan(k, mode, step)
+                    h0.build_grid(P)
+                    h0.alm_accumulate()
+                    h0.contract()
+                    c0 = h0.multipoles([(0, 0, 0)]).cpu().numpy()
+                    h0.sync()
+                    assert h0.pair_count() == res.npairs
+                    h0.close()
+                    assert rel_err(c0, ref0) < 1e-12, (k, mode, step)
+                    h4 = T.Handle(box, edges, 4, precision=prec)
+                    h4.set_plan(k, mode, step)
+                    h4.build_grid(P)
+                    h4.alm_accumulate()
+                    h4.contract()
+                    c4 = h4.multipoles(mults).cpu().numpy()
+                    h4.sync()
+                    h4.close()
+                    assert rel_err(c4, ref4) < 1e-5, (PNAME[prec], k, mode, step, rel_err(c4, ref4))
+
+
 # ------------------------------------------------------------------ long lists
 
 
