@@ -179,10 +179,23 @@ tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2
  * for bit. Until the next tpcf_build_grid the handle then refuses, with
  * TPCF_ERR_STATE, a tpcf_contract export of NNN^m and tpcf_multipoles triples
  * with L > lmax.
+ * A catalogue with a non-finite coordinate does not stop the others: its
+ * results are NaN, its status (tpcf_catalog_status) TPCF_ERR_DEVICE, the other
+ * catalogues' results are complete and equal those of a batch without it, and
+ * the call returns TPCF_ERR_DEVICE naming the catalogues. Any other error
+ * leaves d_out undefined.
  */
 tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n,
                               const int64_t* h_n_data, const double* d_pos, const double* d_w,
                               int32_t n_mult, const int32_t* h_l1l2L, double* d_out);
+
+/*
+ * Status of each catalogue of the last tpcf_run_catalogs that returned after
+ * its argument checks: h_status (host, ncat int32) gets TPCF_OK or
+ * TPCF_ERR_DEVICE (non-finite positions). ncat must equal that call's.
+ * TPCF_ERR_ARG on a NULL h_status or a different ncat.
+ */
+tpcf_status tpcf_catalog_status(tpcf_handle h, int32_t ncat, int32_t* h_status);
 
 /*
  * Anisotropic 2PCF pair counts DD(r, mu) (Sec. 4.1) of the catalogue given to

@@ -85,7 +85,8 @@ struct tpcf_handle_s {
     bool self_lo = false;  // tpcf_run_catalogs with multipoles of L <= lmax only (no per-m export)
     bool self_cut = false;  // the summed self moments stop at order lmax (set by such a run)
     DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
-        d_catid, d_flag, d_istart, d_icell, d_icat, d_scanw;
+        d_catid, d_flag, d_istart, d_icell, d_icat, d_scanw, d_catbad;
+    std::vector<int32_t> cat_status;  // per catalogue of the last tpcf_run_catalogs
     std::vector<int> item_cat;       // [ncat+1] first work item of each catalogue
 
     // pair pass
@@ -550,13 +551,15 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_perm, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_catid, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_flag, sizeof(int) * 4)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_catbad, sizeof(int) * h->ncat)) != TPCF_OK) return st;
     Timer t;
     t_begin(h, 0, t);
     HIPCHK(launch_fill_i32(P<int>(h->d_count), M + 1, 0, h->stream));
     HIPCHK(launch_fill_i32(P<int>(h->d_cursor), M + 1, 0, h->stream));
     HIPCHK(launch_fill_i32(P<int>(h->d_flag), 4, 0, h->stream));
+    HIPCHK(launch_fill_i32(P<int>(h->d_catbad), h->ncat, 0, h->stream));
     HIPCHK(launch_grid_assign(d_pos, d_w, N, P<int64_t>(h->d_pt_off), h->ncat, h->g, P<int>(h->d_cellid),
-                              P<int>(h->d_count), P<int>(h->d_flag), h->stream));
+                              P<int>(h->d_count), P<int>(h->d_flag), P<int>(h->d_catbad), h->stream));
     HIPCHK(launch_grid_scan(P<int>(h->d_count), M, P<int>(h->d_start), P<int>(h->d_scanw), h->stream));
     HIPCHK(launch_grid_scatter(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_cursor),
                                P<int>(h->d_tmp), h->stream));
@@ -1029,9 +1032,12 @@ tpcf_status validate_config(const tpcf_config* c) {
 // Steps 1-3 (and with d_out step 4) of ncat catalogues, in groups of whole
 // catalogues whose points fit a quarter of the workspace. self_lo: every
 // multipole asked for has L <= lmax.
+// A catalogue with non-finite positions (status != nullptr): its status
+// becomes TPCF_ERR_DEVICE, its output NaN, and the other catalogues of its
+// group are run again without it.
 tpcf_status run_groups(tpcf_handle h, int32_t ncat, const int64_t* h_n, const int64_t* h_n_data,
                        const double* d_pos, const double* d_w, bool self_lo, int32_t n_mult,
-                       const int32_t* h_l1l2L, double* d_out) {
+                       const int32_t* h_l1l2L, double* d_out, int32_t* status) {
     tpcf_status st;
     const int64_t per_point = 96;
     const int64_t max_pts = std::max<int64_t>(1, std::min<int64_t>((h->limit / 4) / per_point, (1LL << 31) - 1));
@@ -1046,7 +1052,38 @@ tpcf_status run_groups(tpcf_handle h, int32_t ncat, const int64_t* h_n, const in
         h->stage = 0;
         if ((st = build_grid_group(h, d_pos + 3 * pos_off, d_w ? d_w + pos_off : nullptr, n, nd)) != TPCF_OK)
             return st;
-        if ((st = check_nonfinite(h)) != TPCF_OK) return st;
+        if ((st = check_nonfinite(h)) != TPCF_OK) {
+            if (!status || st != TPCF_ERR_DEVICE) return st;
+            // which catalogues: mark them, NaN their outputs, rerun the runs of good ones
+            std::vector<int> bad(c1 - c0, 0);
+            HIPCHK(hipMemcpyAsync(bad.data(), h->d_catbad.p, sizeof(int) * bad.size(), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            int r0 = c0;
+            for (int c = c0; c <= c1; ++c) {
+                const bool is_bad = c < c1 && bad[c - c0] > 0;
+                if (c == c1 || is_bad) {
+                    if (c > r0) {
+                        // the good catalogues r0 .. c-1
+                        int64_t o = pos_off;
+                        for (int q = c0; q < r0; ++q) o += h_n[q];
+                        if ((st = run_groups(h, c - r0, h_n + r0, h_n_data + r0, d_pos + 3 * o, d_w ? d_w + o : nullptr,
+                                             self_lo, n_mult, h_l1l2L, d_out ? d_out + per_out * r0 : nullptr,
+                                             status + r0)) != TPCF_OK)
+                            return st;
+                    }
+                    if (is_bad) {
+                        status[c] = TPCF_ERR_DEVICE;
+                        if (d_out && per_out > 0)
+                            HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(d_out + per_out * c), per_out,
+                                                   0x7ff8000000000000ull, h->stream));
+                    }
+                    r0 = c + 1;
+                }
+            }
+            pos_off += pts;
+            c0 = c1;
+            continue;
+        }
         if ((st = plan_chunks(h)) != TPCF_OK) return st;
         // The self moments of order above lmax cancel from every multipole
         // of L <= lmax (their coefficients sum to zero over m), and this run
@@ -1128,7 +1165,7 @@ void tpcf_destroy(tpcf_handle h) {
     DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_runs, &h->d_shift_f, &h->d_goff,
                      &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
                      &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
-                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_scanw, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
+                     &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_scanw, &h->d_catbad, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag,
                      &h->d_xiq, &h->d_xicoef, &h->d_xirr, &h->d_xiruns, &h->d_covx, &h->d_covoff,
@@ -1260,7 +1297,30 @@ tpcf_status tpcf_run_catalogs(tpcf_handle h, int32_t ncat, const int64_t* h_n, c
         if (h_n_data[c] < 3) return fail(h, TPCF_ERR_ARG, "n_data must be >= 3");
     }
     HIPCHK(hipSetDevice(h->device));
-    return run_groups(h, ncat, h_n, h_n_data, d_pos, d_w, max_L <= h->lmax, n_mult, h_l1l2L, d_out);
+    h->cat_status.assign(ncat, TPCF_OK);
+    if ((st = run_groups(h, ncat, h_n, h_n_data, d_pos, d_w, max_L <= h->lmax, n_mult, h_l1l2L, d_out,
+                         h->cat_status.data())) != TPCF_OK)
+        return st;
+    std::string badlist;
+    int nbad = 0;
+    for (int c = 0; c < ncat; ++c)
+        if (h->cat_status[c] != TPCF_OK) {
+            if (nbad < 8) badlist += (nbad ? ", " : "") + std::to_string(c);
+            ++nbad;
+        }
+    if (nbad)
+        return fail(h, TPCF_ERR_DEVICE, std::to_string(nbad) + " catalogue(s) with non-finite positions (" + badlist +
+                                            (nbad > 8 ? ", ..." : "") +
+                                            "): their outputs are NaN, the others are complete (tpcf_catalog_status)");
+    return TPCF_OK;
+}
+
+tpcf_status tpcf_catalog_status(tpcf_handle h, int32_t ncat, int32_t* h_status) {
+    if (!alive(h)) return TPCF_ERR_ARG;
+    if (!h_status || ncat != (int32_t)h->cat_status.size())
+        return fail(h, TPCF_ERR_ARG, "h_status is NULL or ncat differs from the last tpcf_run_catalogs");
+    std::copy(h->cat_status.begin(), h->cat_status.end(), h_status);
+    return TPCF_OK;
 }
 
 tpcf_status tpcf_xi_count(tpcf_handle h, int32_t nmu, int64_t* d_counts) {
@@ -1635,7 +1695,8 @@ tpcf_status tpcf_autotune_plan(tpcf_handle h, int32_t ncat, const int64_t* h_n, 
                 bool fits = true;
                 for (int rep = 0; rep < 2 && st == TPCF_OK; ++rep) {
                     if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(h, TPCF_ERR_DEVICE, "hipEventRecord"); break; }
-                    if ((st = run_groups(h, ncat, h_n, h_n_data, d_pos, d_w, true, 0, nullptr, nullptr)) != TPCF_OK) {
+                    if ((st = run_groups(h, ncat, h_n, h_n_data, d_pos, d_w, true, 0, nullptr, nullptr, nullptr)) !=
+                        TPCF_OK) {
                         // a candidate whose lists do not fit the workspace is not admissible
                         if (st == TPCF_ERR_ALLOC) {
                             HIPCHK(hipStreamSynchronize(h->stream));

@@ -36,18 +36,19 @@ __device__ inline int find_cat(const int64_t* off, int ncat, int64_t i) {
 __global__ void k_grid_assign(const double* __restrict__ pos, int64_t n,
                               const int64_t* __restrict__ pt_off, int ncat, Grid g,
                               int* __restrict__ cellid, int* __restrict__ count,
-                              int* __restrict__ nonfinite) {
+                              int* __restrict__ nonfinite, int* __restrict__ catbad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    int c = find_cat(pt_off, ncat, i);
     if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
         atomicAdd(nonfinite, 1);
+        atomicAdd(&catbad[c], 1);
         x = y = z = 0.0;
     }
     x = wrap_coord(x, g.box);
     y = wrap_coord(y, g.box);
     z = wrap_coord(z, g.box);
-    int c = find_cat(pt_off, ncat, i);
     int id = c * g.ncell + (cell_of(x, g) * g.nc + cell_of(y, g)) * g.nc + cell_of(z, g);
     cellid[i] = id;
     atomicAdd(&count[id], 1);
@@ -243,11 +244,11 @@ hipError_t launch_items_cat(const int* item_start, int ncat, int ncell, int* ite
 }
 
 hipError_t launch_grid_assign(const double* pos, const double*, int64_t n, const int64_t* pt_off,
-                              int ncat, Grid g, int* cellid, int* count, int* nonfinite,
+                              int ncat, Grid g, int* cellid, int* count, int* nonfinite, int* catbad,
                               hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grid_assign, dim3(nblk(n, 256)), dim3(256), 0, s, pos, n, pt_off, ncat, g,
-                       cellid, count, nonfinite);
+                       cellid, count, nonfinite, catbad);
     return hipGetLastError();
 }
 

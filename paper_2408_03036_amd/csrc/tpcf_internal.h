@@ -49,8 +49,9 @@ struct CatArrays {
 
 // ---------------------------------------------------------------- launchers
 // Grid build (tpcf_grid.hip)
+// nonfinite counts points with a non-finite coordinate, catbad[c] those of catalogue c
 hipError_t launch_grid_assign(const double* pos, const double* w, int64_t n, const int64_t* pt_off,
-                              int ncat, Grid g, int* cellid, int* count, int* nonfinite,
+                              int ncat, Grid g, int* cellid, int* count, int* nonfinite, int* catbad,
                               hipStream_t s);
 // Exclusive scan of m counts into start[0..m]; work holds grid_scan_work_ints(m) ints.
 hipError_t launch_grid_scan(const int* count, int64_t m, int* start, int* work, hipStream_t s);

@@ -39,7 +39,7 @@ EXPORTS = ["tpcf_create", "tpcf_destroy", "tpcf_last_error", "tpcf_build_grid",
            "tpcf_run_catalogs", "tpcf_sync", "tpcf_pair_count", "tpcf_rebinned_count", "tpcf_set_timing",
            "tpcf_stage_times", "tpcf_xi_count", "tpcf_xi_multipoles", "tpcf_triangle_index",
            "tpcf_covariance", "tpcf_covariance_noalloc", "tpcf_precision_matrix", "tpcf_percival_m1", "tpcf_edge_correct_isotropic", "tpcf_edge_correct",
-           "tpcf_autotune", "tpcf_autotune_plan", "tpcf_set_plan", "tpcf_get_plan"]
+           "tpcf_autotune", "tpcf_autotune_plan", "tpcf_set_plan", "tpcf_get_plan", "tpcf_catalog_status"]
 
 
 class TpcfError(RuntimeError):
@@ -95,6 +95,8 @@ def load():
     lib.tpcf_multipoles.restype = st
     lib.tpcf_run_catalogs.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp]
     lib.tpcf_run_catalogs.restype = st
+    lib.tpcf_catalog_status.argtypes = [vp, i32, vp]
+    lib.tpcf_catalog_status.restype = st
     lib.tpcf_sync.argtypes = [vp]
     lib.tpcf_sync.restype = st
     lib.tpcf_pair_count.argtypes = [vp, ctypes.POINTER(i64)]
@@ -167,7 +169,7 @@ class Handle:
         self.nbins = self.edges.shape[0] - 1
         self.lmax = int(lmax)
         self.box = float(box)
-        self.precision = int(precision)
+        self.prec = int(precision)
         self.flags = int(flags)
         self.device = int(device)
         if stream is None:
@@ -234,7 +236,7 @@ class Handle:
         dens = mean / self.box ** 3 * float(self.edges[-1]) ** 3
         eh = hashlib.sha1(self.edges.tobytes()).hexdigest()[:10]
         b = lambda x: int(round(math.log2(max(x, 1e-9))))
-        return (f"{arch}|prec{self.precision}|flags{self.flags}|lmax{self.lmax}|nb{self.nbins}|edges{eh}|"
+        return (f"{arch}|prec{self.prec}|flags{self.flags}|lmax{self.lmax}|nb{self.nbins}|edges{eh}|"
                 f"box{self.box:g}|ncat2^{b(len(sizes))}|n2^{b(mean)}|nr3_2^{b(dens)}")
 
     def autotune_plan(self, pos, w=None, sizes=None, n_data=None, cache=None):
@@ -328,6 +330,14 @@ class Handle:
                                              ctypes.c_void_p(nd.ctypes.data), _ptr(pos), _ptr(w),
                                              tr.shape[0], ctypes.c_void_p(tr.ctypes.data),
                                              _ptr(out)))
+        return out
+
+    def catalog_status(self, ncat):
+        """Per-catalogue status (int32, 0 = ok) of the last run_catalogs; a
+        catalogue with non-finite positions has TPCF_ERR_DEVICE and NaN
+        results while the others complete (run_catalogs itself raises)."""
+        out = np.zeros(int(ncat), dtype=np.int32)
+        self._chk(self.lib.tpcf_catalog_status(self.h, int(ncat), ctypes.c_void_p(out.ctypes.data)))
         return out
 
     # -- anisotropic 2PCF (Sec. 4.1) ----------------------------------

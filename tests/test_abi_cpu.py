@@ -132,6 +132,7 @@ def test_host_helpers_match_oracle(lib):
     assert lib.tpcf_autotune_plan(None, 1, None, None, None, None, None, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_set_plan(None, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_get_plan(None, None) == T.TPCF_ERR_ARG
+    assert lib.tpcf_catalog_status(None, 1, None) == T.TPCF_ERR_ARG
     assert lib.tpcf_edge_correct_isotropic(None, 3, None, None, None) == T.TPCF_ERR_ARG
 
 
@@ -146,6 +147,8 @@ def test_foreign_and_dead_handles_are_refused_unread(lib):
     assert lib.tpcf_sync(bogus) == T.TPCF_ERR_ARG
     assert lib.tpcf_alm_accumulate(bogus) == T.TPCF_ERR_ARG
     assert lib.tpcf_contract(bogus, None) == T.TPCF_ERR_ARG
+    st = (ctypes.c_int32 * 4)()
+    assert lib.tpcf_catalog_status(bogus, 4, st) == T.TPCF_ERR_ARG
     assert b"invalid or destroyed" in lib.tpcf_last_error(bogus)
     lib.tpcf_destroy(bogus)
     lib.tpcf_destroy(bogus)

@@ -350,6 +350,44 @@ def test_nonfinite_positions_reported(torch):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_MIXED_BF16X3])
+def test_bad_catalogue_isolated_in_batch(torch, prec):
+    """A batch of five catalogues, the second and the last with a non-finite
+    coordinate: run_catalogs reports those two (TPCF_ERR_DEVICE, status per
+    catalogue), their results are NaN, and the other three equal, bit for bit,
+    those of a batch of only the good catalogues."""
+    box, edges, lmax = 150.0, np.linspace(10.0, 40.0, 4), 4
+    sizes = [1500, 700, 2600, 900, 1100]
+    cats = [C.zeldovich(n, box, 3.0, 0.8, 300 + i, grid=32) for i, n in enumerate(sizes)]
+    cats[1][333, 2] = np.nan
+    cats[4][0, 0] = np.inf
+    mults = O.all_multipoles(lmax, 2)
+    h = T.Handle(box, edges, lmax, precision=prec)
+    out = torch.zeros((5, len(mults), 3, 3), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(T.TpcfError) as e:
+        h.run_catalogs(sizes, sizes, gpu(torch, np.vstack(cats)), None, mults, out=out)
+    assert e.value.status == T.TPCF_ERR_DEVICE
+    assert "(1, 4)" in str(e.value)
+    st = h.catalog_status(5)
+    assert st.tolist() == [0, T.TPCF_ERR_DEVICE, 0, 0, T.TPCF_ERR_DEVICE]
+    h.sync()
+    got = out.cpu().numpy()
+    assert np.isnan(got[[1, 4]]).all()
+    good = [0, 2, 3]
+    ref = h.run_catalogs([sizes[i] for i in good], [sizes[i] for i in good],
+                         gpu(torch, np.vstack([cats[i] for i in good])), None, mults)
+    h.sync()
+    assert h.catalog_status(3).tolist() == [0, 0, 0]
+    with pytest.raises(T.TpcfError) as e:
+        h.catalog_status(5)
+    assert e.value.status == T.TPCF_ERR_ARG
+    ref = ref.cpu().numpy()
+    for k, i in enumerate(good):
+        assert np.array_equal(got[i], ref[k]), i
+    say(f"  bad catalogues isolated ({PNAME[prec]}): statuses {st.tolist()}")
+    h.close()
+
+
 def test_out_of_order_calls(torch):
     h = T.Handle(50.0, np.array([1.0, 5.0]), 2)
     with pytest.raises(T.TpcfError) as e:
