@@ -327,9 +327,12 @@ def bench_xi(args):
 
 def bench_ss(args):
     """Szapudi-Szalay estimator with explicit randoms at 50x (the paper's ratio):
-    a data-minus-randoms run and a randoms run on the isotropic schedule, then
-    the edge correction, on 1e4 clustered points with 5e5 randoms in a 400
-    Mpc/h box (the paper's halo density), 12 bins over [30, 150], l <= 4."""
+    a data-minus-randoms run and a randoms run, then the edge correction, on
+    1e4 clustered points with 5e5 randoms in a 400 Mpc/h box (the paper's halo
+    density), 12 bins over [30, 150], l <= 4. By default the isotropic
+    schedule and its correction; with --aniso the full anisotropic pass, the
+    per-m sums of both runs and the tripolar correction of every multipole
+    with L <= 2."""
     import torch
     from paper_2408_03036_amd import catalogs as C
     from paper_2408_03036_amd import tpcf as T
@@ -348,18 +351,40 @@ def bench_ss(args):
     w = torch.from_numpy(C.dr_weights(nd, nr)).cuda()
     prec = {"bf16x3": T.PREC_MIXED_BF16X3, "bf16x6": T.PREC_MIXED_BF16X6, "fp32": T.PREC_FP32,
             "fp64": T.PREC_FP64}[args.precision]
-    # the neighbour lists of 1e5 randoms per primary need room: 200 GiB of the 288 GB
-    hN = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
-    hR = T.Handle(box, edges, lmax, precision=prec, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+    aniso = bool(getattr(args, "aniso", False))
+    flags = 0 if aniso else T.F_ISOTROPIC
+    mults = all_multipoles(lmax, 2) if aniso else iso
+
+    def handles(p):
+        # the neighbour lists of 1e5 randoms per primary need room: 200 GiB of the 288 GB
+        return (T.Handle(box, edges, lmax, precision=p, flags=flags, workspace_limit=200 << 30),
+                T.Handle(box, edges, lmax, precision=p, flags=flags, workspace_limit=200 << 30))
+
+    def make_step(hN, hR):
+        if not aniso:
+            def step():
+                Nm = hN.run_catalogs([nd + nr], [nd], pos, w, iso)
+                Rm = hR.run_catalogs([nr], [nr], Rp, None, iso)
+                return hN.edge_correct_isotropic(Nm[0], Rm[0])
+            return step
+
+        def step():
+            # the per-m sums NNN^m of both runs, then the tripolar edge correction
+            hN.build_grid(pos, w, nd)
+            hN.alm_accumulate()
+            nnnN = hN.contract(export=True)
+            hR.build_grid(Rp, None, nr)
+            hR.alm_accumulate()
+            nnnR = hR.contract(export=True)
+            return hN.edge_correct(nnnN, nd, nnnR, nr, mults)[0]
+        return step
+
+    hN, hR = handles(prec)
     plans = {"data_minus_randoms": tune(hN, np.array([nd + nr]), pos, w, [nd], args),
              "randoms": tune(hR, np.array([nr]), Rp, None, [nr], args)}
     hN.set_timing(True)
     hR.set_timing(True)
-
-    def step():
-        Nm = hN.run_catalogs([nd + nr], [nd], pos, w, iso)
-        Rm = hR.run_catalogs([nr], [nr], Rp, None, iso)
-        return hN.edge_correct_isotropic(Nm[0], Rm[0])
+    step = make_step(hN, hR)
 
     for _ in range(args.warmup):
         step()
@@ -383,14 +408,14 @@ def bench_ss(args):
     if not args.no_fp64 and prec != T.PREC_FP64:
         # the same step on the plain FP64 path: time and the accuracy of this precision
         print("[bench] ss fp64 comparison", file=sys.stderr, flush=True)
-        hN = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
-        hR = T.Handle(box, edges, lmax, precision=T.PREC_FP64, flags=T.F_ISOTROPIC, workspace_limit=200 << 30)
+        hN, hR = handles(T.PREC_FP64)
         tune(hN, np.array([nd + nr]), pos, w, [nd], args)
         tune(hR, np.array([nr]), Rp, None, [nr], args)
-        step()  # the first step allocates the workspace
+        step64 = make_step(hN, hR)
+        step64()  # the first step allocates the workspace
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        z64 = step()
+        z64 = step64()
         torch.cuda.synchronize()
         dt64 = time.perf_counter() - t0
         hN.close()
@@ -403,7 +428,8 @@ def bench_ss(args):
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if prec != T.PREC_FP64 else "f64", "data": "synthetic",
         "config": {"workload": f"{nd} Zel'dovich+RSD points + {nr} randoms (50x), {box:.0f} Mpc/h box, 12 bins "
-                               f"[30,150] Mpc/h, isotropic l <= {lmax}, edge-corrected",
+                               f"[30,150] Mpc/h, " + (f"anisotropic lmax {lmax}, {len(mults)} multipoles L <= 2, tripolar "
+                               "edge correction" if aniso else f"isotropic l <= {lmax}, edge-corrected"),
                    "precision": args.precision, "pairs_per_step": int(pairs), "parallelism": "single GPU"},
         "stages_ms": {k: (msN[i] + msR[i]) / args.steps for i, k in
                       enumerate(["grid_ms", "pair_bin_ms", "pair_alm_ms", "contract_ms", "finalize_ms"])},
@@ -619,6 +645,8 @@ def main():
     ap.add_argument("--refine", type=int, default=0, help="fixed grid refinement (no plan tuning)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan")
     ap.add_argument("--plan-cache", default=None, help="JSON plan cache to read and extend")
+    ap.add_argument("--aniso", action="store_true",
+                    help="with --workload ss: the anisotropic pass and the tripolar edge correction")
     ap.add_argument("--workload", default="3pcf", choices=["3pcf", "xi", "cov", "ss", "c5"],
                     help="3pcf: the batched 3PCF run (default); xi: the anisotropic 2PCF; "
                          "c5: data + 5x randoms catalogues of the large sweep (a timed subset); "

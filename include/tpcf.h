@@ -97,10 +97,16 @@ enum {
 
 typedef struct {
     double box;              /* L > 0, finite; the box is periodic in x, y and z             */
-    int32_t nbins;           /* 1 .. 32 radial bins                                           */
+    int32_t nbins;           /* 1 .. 32 radial bins (a bin's per-primary counters and
+                                predicted regions are one 32-entry LDS row per primary in
+                                the binning kernel)                                           */
     const double* h_edges;   /* nbins+1 strictly increasing edges, edges[0] >= 0,
                                 edges[nbins] <= box/2 (minimum image); copied at create       */
-    int32_t lmax;            /* 0 .. 12                                                       */
+    int32_t lmax;            /* 0 .. 12. The harmonic pass keeps every a_lm of a (primary,
+                                bin) list in one lane's registers, split over two launches
+                                by m range above lmax 10 (FP32) or 6 (FP64); above 12 a
+                                half would no longer fit one lane. The paper's multipoles
+                                need lmax 3, and the benchmark shapes 10.                     */
     int32_t precision;       /* tpcf_precision                                                */
     uint32_t flags;          /* TPCF_F_* bits                                                 */
     int32_t grid_refine;     /* cells per r_max along an axis for the neighbour grid,
