@@ -102,11 +102,12 @@ typedef struct {
                                 the binning kernel)                                           */
     const double* h_edges;   /* nbins+1 strictly increasing edges, edges[0] >= 0,
                                 edges[nbins] <= box/2 (minimum image); copied at create       */
-    int32_t lmax;            /* 0 .. 12. The harmonic pass keeps every a_lm of a (primary,
-                                bin) list in one lane's registers, split over two launches
-                                by m range above lmax 10 (FP32) or 6 (FP64); above 12 a
-                                half would no longer fit one lane. The paper's multipoles
-                                need lmax 3, and the benchmark shapes 10.                     */
+    int32_t lmax;            /* 0 .. 16. The harmonic pass keeps the a_lm of a (primary,
+                                bin) list in one lane's registers; above lmax 10 (FP32) or
+                                6 (FP64) it splits the m range over 2 launches, and from 13
+                                over 3 (FP32) or 4 (FP64), each rereading the lists. With
+                                weights and nbins (lmax + 1) > 512 the split-BF16
+                                precisions contract on FP32 MFMA.                          */
     int32_t precision;       /* tpcf_precision                                                */
     uint32_t flags;          /* TPCF_F_* bits                                                 */
     int32_t grid_refine;     /* cells per r_max along an axis for the neighbour grid,

@@ -1161,8 +1161,16 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t s) {
     switch (a.mode) {
         case 0: return launch_contract_mode<0>(a, s);
         case 1: return launch_contract_mode<1>(a, s);
-        case 2: return launch_contract_bf16<2>(a, s);
-        case 3: return launch_contract_bf16<3>(a, s);
+        case 2:
+        case 3: {
+            // a split-BF16 step must stage at least 16 primaries of every
+            // column in the threads' registers (nbins (lmax + 1) <= 512 with
+            // weights); beyond that the FP32 MFMA contraction runs instead
+            const int K0 = a.nb * (a.lmax + 1);
+            if (bf_plan(a.mode == 2 ? 2 : 3, (K0 + 31) / 32 * 32, !a.unit_weights, a.ks_max).KS == 0)
+                return launch_contract_mode<1>(a, s);
+            return a.mode == 2 ? launch_contract_bf16<2>(a, s) : launch_contract_bf16<3>(a, s);
+        }
         default: return hipErrorInvalidValue;
     }
 }
@@ -1174,7 +1182,7 @@ size_t contract_lds_bytes(int mode, int nb, int lmax) {
         case 1: return contract_lds<1>((K0 + 31) / 32 * 32);
         default: {
             const BfPlan pl = bf_plan(mode == 2 ? 2 : 3, (K0 + 31) / 32 * 32, true);
-            return pl.KS ? pl.lds : (size_t)-1;
+            return pl.KS ? pl.lds : contract_lds<1>((K0 + 31) / 32 * 32);
         }
     }
 }

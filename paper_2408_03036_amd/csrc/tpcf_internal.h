@@ -7,7 +7,7 @@
 namespace tpcf {
 
 constexpr int kMaxBins = 32;
-constexpr int kMaxLmax = 12;
+constexpr int kMaxLmax = 16;
 constexpr int kMaxRuns = 2 * 81;   // stencil column runs after z-wrap splitting (grid_refine <= 4)
 constexpr int kMaxCodes = 729;     // (2k+1)^3 stencil offsets for grid_refine <= 4
 constexpr int kWave = 64;

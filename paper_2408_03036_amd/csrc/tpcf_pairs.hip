@@ -607,11 +607,53 @@ __host__ __device__ constexpr int m_split(int lmax) {
     return M;
 }
 
+// Finer splits above lmax 12: the m range in np parts (3 or 4), the self
+// moments with part 0, chosen to minimise the largest part's values. Returns
+// the first m of part p (p = np gives lmax + 1).
+__host__ __device__ constexpr int values_of_m(int lmax, int m) { return m == 0 ? lmax + 1 : 2 * (lmax - m + 1); }
+__host__ __device__ constexpr int part_first_m(int lmax, int np, int p) {
+    if (p <= 0) return 0;
+    if (p >= np) return lmax + 1;
+    // cumulative values before m = M (the self moments count with m = 0)
+    int cum[64] = {};
+    cum[0] = 2 * lmax + 1;
+    for (int m = 0; m <= lmax; ++m) cum[m + 1] = cum[m] + values_of_m(lmax, m);
+    int best = 1 << 30, b1 = 1, b2 = 2, b3 = 3;
+    for (int x1 = 1; x1 <= lmax; ++x1)
+        for (int x2 = x1 + 1; x2 <= (np >= 3 ? lmax : x1 + 1); ++x2)
+            for (int x3 = x2 + 1; x3 <= (np >= 4 ? lmax : x2 + 1); ++x3) {
+                const int e2 = np >= 3 ? x2 : lmax + 1, e3 = np >= 4 ? x3 : lmax + 1;
+                int worst = cum[x1];
+                if (np >= 3 && cum[e2] - cum[x1] > worst) worst = cum[e2] - cum[x1];
+                if (np >= 4 && cum[e3] - cum[e2] > worst) worst = cum[e3] - cum[e2];
+                const int last = np >= 4 ? e3 : (np >= 3 ? e2 : x1);
+                if (cum[lmax + 1] - cum[last] > worst) worst = cum[lmax + 1] - cum[last];
+                if (worst < best) {
+                    best = worst;
+                    b1 = x1;
+                    b2 = x2;
+                    b3 = x3;
+                }
+            }
+    return p == 1 ? b1 : (p == 2 ? b2 : b3);
+}
+
+// Part G of the m range: G = 0 the whole range; G = 1, 2 the two halves of
+// m_split; G = 3 .. 5 three parts; G = 6 .. 9 four parts.
+__host__ __device__ constexpr int part_np(int G) { return G == 0 ? 1 : (G <= 2 ? 2 : (G <= 5 ? 3 : 4)); }
+__host__ __device__ constexpr int part_ix(int G) { return G == 0 ? 0 : (G <= 2 ? G - 1 : (G <= 5 ? G - 3 : G - 6)); }
+__host__ __device__ constexpr int part_mlo(int lmax, int G) {
+    return G <= 2 ? (G == 2 ? m_split(lmax) + 1 : 0) : part_first_m(lmax, part_np(G), part_ix(G));
+}
+__host__ __device__ constexpr int part_mhi(int lmax, int G) {
+    return G <= 2 ? (G == 1 ? m_split(lmax) : lmax) : part_first_m(lmax, part_np(G), part_ix(G) + 1) - 1;
+}
+
 template <typename T, int LMAX, int G>
 struct Acc {
-    static constexpr int MLO = G == 2 ? m_split(LMAX) + 1 : 0;
-    static constexpr int MHI = G == 1 ? m_split(LMAX) : LMAX;
-    static constexpr bool SELF = G != 2;
+    static constexpr int MLO = part_mlo(LMAX, G);
+    static constexpr int MHI = part_mhi(LMAX, G);
+    static constexpr bool SELF = MLO == 0;
     static constexpr int V0 = value_offset(LMAX, MLO);
     static constexpr int V1 = value_offset(LMAX, MHI + 1);
     static constexpr int NA = V1 - V0;            // a_lm values held
@@ -638,13 +680,26 @@ __host__ __device__ constexpr int self_top(int lmax, bool slo) { return slo ? lm
 // moments of order L <= lmax then equal the m = 0 sums and are not
 // accumulated twice (the caller copies them). With SLO the self moments stop
 // at order lmax (those above are left 0; see self_top).
+//
+// Above lmax 12 the orders m >= 1 are accumulated in the monic basis itself,
+// by the recurrence per pair (direct_m). The Chebyshev form bounds the error
+// of a converted sum by q_l^m(1) times that of the Chebyshev sums, and for
+// large m the Gegenbauer polynomial q_l^m peaks at z = +-1 far above its
+// values elsewhere (by about 1800 at l = 16, m = 8), which at lmax 16 cost
+// FP32 sums a few 1e-5 of the largest coefficient; the recurrence is stable.
+__host__ __device__ constexpr bool direct_m(int lmax) { return lmax >= 13; }
+
 template <typename T, int LMAX, int G, bool UNIT, bool SLO = false>
 __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) {
     using AC = Acc<T, LMAX, G>;
     constexpr int MLO = AC::MLO, MHI = AC::MHI, V0 = AC::V0;
     constexpr bool SHARE = UNIT && MLO == 0 && AC::SELF;  // s[l] == a[l] for l <= lmax
     constexpr int STOP = self_top(LMAX, SLO);
-    constexpr int KTOP = AC::SELF ? (STOP > LMAX - MLO ? STOP : LMAX - MLO) : LMAX - MLO;  // highest Chebyshev degree used
+    constexpr bool DIRECT = direct_m(LMAX);
+    // highest Chebyshev degree used: the m = 0 sums, the self moments, and
+    // the orders m >= MLO unless they are accumulated directly
+    constexpr int KCH = DIRECT ? (MLO == 0 ? LMAX : 0) : LMAX - MLO;
+    constexpr int KTOP = AC::SELF ? (STOP > KCH ? STOP : KCH) : KCH;
     T t[KTOP + 1];
     t[0] = (T)1;
     if constexpr (KTOP >= 1) t[1] = z;
@@ -675,10 +730,27 @@ __device__ __forceinline__ void add_hit(Acc<T, LMAX, G>& A, T x, T y, T z, T w) 
             if (m >= MLO) {
                 const int vo = value_offset(LMAX, m) - V0;
                 const int nl = LMAX - m + 1;
+                if constexpr (DIRECT) {
+                    // q_m = 1, q_{m+1} = z, q_l = z q_{l-1} - beta(l, m) q_{l-2}
+                    T q0 = (T)1, q1 = z;
+                    A.a[vo] += cr;
+                    A.a[vo + nl] += ci;
 #pragma unroll
-                for (int k = 0; k < nl; ++k) {
-                    A.a[vo + k] = fma(t[k], cr, A.a[vo + k]);
-                    A.a[vo + nl + k] = fma(t[k], ci, A.a[vo + nl + k]);
+                    for (int k = 1; k < nl; ++k) {
+                        if (k >= 2) {
+                            const T q2 = fma(z, q1, -(T)beta_d(m + k, m) * q0);
+                            q0 = q1;
+                            q1 = q2;
+                        }
+                        A.a[vo + k] = fma(q1, cr, A.a[vo + k]);
+                        A.a[vo + nl + k] = fma(q1, ci, A.a[vo + nl + k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < nl; ++k) {
+                        A.a[vo + k] = fma(t[k], cr, A.a[vo + k]);
+                        A.a[vo + nl + k] = fma(t[k], ci, A.a[vo + nl + k]);
+                    }
                 }
             }
         }
@@ -703,8 +775,10 @@ template <typename T, int LMAX, int G, bool SLO = false>
 __device__ __forceinline__ void cheb_to_monic(Acc<T, LMAX, G>& A) {
     using AC = Acc<T, LMAX, G>;
     constexpr ChebTable<LMAX> D{};
+    // with direct_m only the m = 0 sums and the self moments are Chebyshev sums
+    constexpr int MTOP = direct_m(LMAX) ? 0 : AC::MHI;
 #pragma unroll
-    for (int m = AC::MLO; m <= AC::MHI; ++m) {
+    for (int m = AC::MLO; m <= MTOP; ++m) {
         const int vo = value_offset(LMAX, m) - AC::V0;
         const int nl = LMAX - m + 1;
         cheb_run_to_monic<T, LMAX>(D, A.a + vo, m, nl);
@@ -997,26 +1071,30 @@ hipError_t launch_alm_one(const AlmArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// FP32 keeps every value of a bin in one lane up to lmax 10; FP64 splits the
-// m range over two launches from lmax 7 on (register budget).
+// FP32 keeps every value of a bin in one lane up to lmax 10, and splits the
+// m range over two launches at lmax 11 and 12 and three from 13; FP64 splits
+// it over two launches from lmax 7 and four from 13 (register budget). Every
+// launch rereads the lists.
+template <typename T, int LMAX, int G0, int NP>
+hipError_t launch_alm_parts(const AlmArgs& a, hipStream_t s) {
+    hipError_t e = launch_alm_one<T, LMAX, G0>(a, s);
+    if constexpr (NP > 1) {
+        if (e != hipSuccess) return e;
+        return launch_alm_parts<T, LMAX, G0 + 1, NP - 1>(a, s);
+    }
+    return e;
+}
+
 template <int LMAX>
 hipError_t launch_alm_lmax(const AlmArgs& a, int fp64, hipStream_t s) {
     if (!fp64) {
-        if constexpr (LMAX <= 10) {
-            return launch_alm_one<float, LMAX, 0>(a, s);
-        } else {
-            hipError_t e = launch_alm_one<float, LMAX, 1>(a, s);
-            if (e != hipSuccess) return e;
-            return launch_alm_one<float, LMAX, 2>(a, s);
-        }
+        if constexpr (LMAX <= 10) return launch_alm_one<float, LMAX, 0>(a, s);
+        else if constexpr (LMAX <= 12) return launch_alm_parts<float, LMAX, 1, 2>(a, s);
+        else return launch_alm_parts<float, LMAX, 3, 3>(a, s);
     } else {
-        if constexpr (LMAX <= 6) {
-            return launch_alm_one<double, LMAX, 0>(a, s);
-        } else {
-            hipError_t e = launch_alm_one<double, LMAX, 1>(a, s);
-            if (e != hipSuccess) return e;
-            return launch_alm_one<double, LMAX, 2>(a, s);
-        }
+        if constexpr (LMAX <= 6) return launch_alm_one<double, LMAX, 0>(a, s);
+        else if constexpr (LMAX <= 12) return launch_alm_parts<double, LMAX, 1, 2>(a, s);
+        else return launch_alm_parts<double, LMAX, 6, 4>(a, s);
     }
 }
 
@@ -1072,6 +1150,10 @@ hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {
         case 10: return launch_alm_lmax<10>(a, fp64, s);
         case 11: return launch_alm_lmax<11>(a, fp64, s);
         case 12: return launch_alm_lmax<12>(a, fp64, s);
+        case 13: return launch_alm_lmax<13>(a, fp64, s);
+        case 14: return launch_alm_lmax<14>(a, fp64, s);
+        case 15: return launch_alm_lmax<15>(a, fp64, s);
+        case 16: return launch_alm_lmax<16>(a, fp64, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -53,7 +53,7 @@ def _create(lib, **kw):
     (dict(edges=[5.0, 4.0, 10.0]), T.TPCF_ERR_RANGE),
     (dict(edges=[-1.0, 10.0]), T.TPCF_ERR_RANGE),
     (dict(edges=[0.0, 101.0]), T.TPCF_ERR_RANGE),
-    (dict(lmax=13), T.TPCF_ERR_RANGE),
+    (dict(lmax=17), T.TPCF_ERR_RANGE),
     (dict(lmax=-1), T.TPCF_ERR_RANGE),
     (dict(precision=4), T.TPCF_ERR_ARG),
     (dict(grid_refine=5), T.TPCF_ERR_RANGE),
@@ -67,14 +67,17 @@ def test_invalid_configs_rejected_before_device(lib, kw, expect):
 
 
 def test_largest_config_fits_every_precision(lib):
-    # 32 bins at lmax 12 is the largest operand: every precision plans its
-    # contraction within LDS, so creation fails only for want of a device
+    # 32 bins at lmax 16 is the largest operand: every precision plans its
+    # contraction within LDS (the split-BF16 ones by running FP32 MFMA where a
+    # weighted step would not fit the threads' registers), so creation fails
+    # only for want of a device
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    for prec in range(4):
-        rc, h = _create(lib, lmax=12, edges=np.linspace(0, 40, 33), precision=prec)
-        assert rc == T.TPCF_ERR_DEVICE, prec
+    for lmax in (12, 13, 16):
+        for prec in range(4):
+            rc, h = _create(lib, lmax=lmax, edges=np.linspace(0, 40, 33), precision=prec)
+            assert rc == T.TPCF_ERR_DEVICE, (lmax, prec)
 
 
 def test_null_arguments(lib):

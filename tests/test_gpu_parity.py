@@ -155,16 +155,16 @@ def test_weighted_data_minus_randoms(torch, prec):
 
 
 @pytest.mark.parametrize("weighted", [False, True])
-@pytest.mark.parametrize("lmax", [8, 12])
+@pytest.mark.parametrize("lmax", [8, 12, 13, 16])
 @pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32, T.PREC_MIXED_BF16X6])
 def test_high_lmax_split_harmonics(torch, prec, lmax, weighted):
     """High orders, where the harmonic pass splits the m range of a list over
-    two launches (FP64 from lmax 7 on, FP32 from lmax 11 on), with unit
-    weights (the self moments of order <= lmax shared with the m = 0 sums) and
-    with data-minus-randoms weights. The FP32 pass is the one of every mixed
-    path; the 3-product split is left to the dense configuration, since its
-    degenerate-triangle error grows with 2l+1 over the few neighbours per bin
-    of this catalogue."""
+    two launches (FP64 from lmax 7 on, FP32 from lmax 11 on) and from lmax 13
+    over three (FP32) or four (FP64), with unit weights (the self moments of
+    order <= lmax shared with the m = 0 sums) and with data-minus-randoms
+    weights. The FP32 pass is the one of every mixed path; the 3-product split
+    is left to the dense configuration, since its degenerate-triangle error
+    grows with 2l+1 over the few neighbours per bin of this catalogue."""
     box, edges = 60.0, np.array([2.0, 5.0, 8.0, 12.0])
     nd, nr = 300, 600
     pos = np.vstack([C.zeldovich(nd, box, 1.5, 0.8, 93, grid=16), C.randoms(nr, box, 94)])
@@ -176,6 +176,46 @@ def test_high_lmax_split_harmonics(torch, prec, lmax, weighted):
     assert npairs == res.npairs
     err = rel_err(got, ref)
     say(f"  lmax {lmax} weighted={weighted} {PNAME[prec]} rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("lmax", [13, 16])
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
+def test_alm_and_nnn_match_oracle_top_lmax(torch, prec, lmax):
+    """Every a_lm and every per-m sum NNN^m at the top of the lmax range, where
+    each list is accumulated in three (FP32) or four (FP64) launches over
+    parts of the m range, against the oracle element by element."""
+    box, edges = 80.0, np.array([3.0, 7.0, 11.0, 15.0])
+    pos = C.zeldovich(1200, box, 2.0, 0.8, 171 + lmax, grid=16)
+    res = O.estimate(pos, box, edges, lmax, want_alm=True)
+    mults = O.all_multipoles(lmax, 2)
+    _, npairs, alm, nnn = run_gpu(torch, pos, box, edges, lmax, mults, prec, want_alm=True, want_nnn=True)
+    assert npairs == res.npairs
+    s1 = lmax + 1
+    mask = np.tril(np.ones((s1, s1), dtype=bool))  # m <= l
+    ea = np.abs(alm[..., mask] - res.alm[..., mask]).max() / np.abs(res.alm).max()
+    ref = res.nnn.real
+    en = np.abs(nnn - ref).max() / np.abs(ref).max()
+    say(f"  lmax {lmax} {PNAME[prec]}: a_lm rel err {ea:.3e}, NNN rel err {en:.3e}")
+    assert ea < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+    assert en < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6])
+def test_largest_operand_weighted_mixed(torch, prec):
+    """32 bins at lmax 16 with weights: one split-BF16 step cannot stage the
+    544 columns, so the contraction runs on FP32 MFMA; the multipoles still
+    match the oracle within the requested precision's tolerance."""
+    box, edges = 60.0, np.linspace(2.0, 14.0, 33)
+    nd, nr = 200, 400
+    pos = np.vstack([C.zeldovich(nd, box, 1.5, 0.8, 181, grid=16), C.randoms(nr, box, 182)])
+    w = C.dr_weights(nd, nr)
+    mults = O.all_multipoles(16, 2)
+    ref, _, res = O.run(pos, box, edges, 16, mults, w=w, n_data=nd)
+    got, npairs, _, _ = run_gpu(torch, pos, box, edges, 16, mults, prec, w=w, n_data=nd)
+    assert npairs == res.npairs
+    err = rel_err(got, ref)
+    say(f"  32 bins, lmax 16, weighted {PNAME[prec]} rel err {err:.3e}")
     assert err < TOL[prec]
 
 

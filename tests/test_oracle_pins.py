@@ -27,7 +27,7 @@ def _rand_dirs(n, seed):
 
 
 def test_ylm_matches_scipy():
-    lmax = 12
+    lmax = 16
     dirs = np.vstack([_rand_dirs(40, 1), [[0, 0, 1.0], [0, 0, -1.0], [1.0, 0, 0]]])
     for v in dirs:
         Y = O.ylm(lmax, v)
@@ -106,6 +106,23 @@ def test_threej_gaunt_quadrature():
 def test_threej_matches_exact_rational():
     for args in [(3, 4, 5, 1, 2, -3), (10, 10, 4, 3, -3, 0), (10, 8, 2, 7, -7, 0), (6, 6, 12, 0, 0, 0)]:
         assert abs(O.wigner3j(*args) - brute.wigner3j_exact(*args)) < 1e-14
+
+
+def test_threej_to_lmax16_matches_exact_rational():
+    """The symbols (l1 l2 L; m -m 0) the multipoles use at the top of the lmax
+    range (l1, l2 <= 16, L <= 32), on a seeded sample, against exact rational
+    arithmetic: Racah's alternating sum must not lose digits there."""
+    rng = np.random.default_rng(16)
+    n = 0
+    for _ in range(600):
+        l1, l2 = (int(v) for v in rng.integers(0, 17, 2))
+        L = int(rng.integers(abs(l1 - l2), l1 + l2 + 1))
+        m = int(rng.integers(0, min(l1, l2) + 1))
+        want = brute.wigner3j_exact(l1, l2, L, m, -m, 0)
+        got = O.wigner3j(l1, l2, L, m, -m, 0)
+        assert abs(got - want) <= 1e-14 * max(abs(want), 1e-3), (l1, l2, L, m)
+        n += want != 0.0
+    assert n > 200
 
 
 # ------------------------------------------------------------------ estimator vs brute force
