@@ -99,6 +99,7 @@ struct tpcf_handle_s {
     float delta = 0.f;    // FP32 guard band in units of the bin width
     int64_t chunk_cap = 0;
     double hits_per_list = 0.0;  // predicted mean length of a (p, b) list
+    double list_grow = 1.0;      // list room found needed beyond the prediction (doubles per overflow)
     unsigned long long list_cap = 0;
     DevBuf d_fix;
     int64_t nfix_total = 0;   // primaries rebinned with exact counts (all chunks since creation)
@@ -608,13 +609,15 @@ tpcf_status plan_chunks(tpcf_handle h) {
     // hit lists: 4-byte entries (FP64 path) or 12/16-byte records (FP32 paths);
     // room for the predicted bin regions of a primary of the densest
     // catalogue (the binning kernel's margin), plus the rare exact rebins (a
-    // list that overflows is rebuilt with twice the room)
+    // pass that runs out of room runs again with twice the room, and the
+    // handle keeps the factor for its later passes)
     const double lelem = list_elem_bytes(h);
     double hits_room = 64.0;
     for (int b = 0; b < h->nb; ++b) {
         const double pred = std::min((double)maxn, maxn / L3 * h->vol[b]);
         hits_room += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
     }
+    hits_room *= h->list_grow;  // room earlier passes of this handle were found to need
     const double list_per = lelem * hits_room;
     h->hits_per_list = hits / h->nb;
     int64_t budget = h->limit / 2;
@@ -694,89 +697,72 @@ tpcf_status plan_chunks(tpcf_handle h) {
     return TPCF_OK;
 }
 
+// Pair pass of one chunk: binning, fix-up of the primaries whose predicted
+// regions overflowed, harmonics. Nothing is read back: a list that ran out of
+// room raises the flag that pair_pass reads after the last chunk.
 tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
-    tpcf_status st;
-    for (int attempt = 0; attempt < 6; ++attempt) {
-        HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), kSlots * 16, 0ull, h->stream));
-        HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 2, 0, h->stream));  // overflow, fix-up count
-        BinArgs b{};
-        b.pf = P<float4>(h->d_pf);
-        b.pd = P<double4>(h->d_pd);
-        b.catid = P<int>(h->d_catid);
-        b.cell_start = P<int>(h->d_start);
-        b.pt_off = P<int64_t>(h->d_pt_off);
-        b.runs = P<StencilRun>(h->d_runs);
-        b.nruns = (int)h->runs.size();
-        b.g = h->g;
-        b.nb = h->nb;
-        b.e2 = P<double>(h->d_e2);
-        b.e2f = P<float>(h->d_e2f);
-        b.guard = P<float>(h->d_guard);
-        b.p_begin = ch.p_begin;
-        b.p_end = ch.p_end;
-        b.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
-        b.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
-        // unit weights with the whole m range in one FP32 lane (lmax <= 10):
-        // the harmonic kernels that read the records (their UNIT forms) take
-        // no weight, so a record is (dx, dy, dz)
-        b.rec3 = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
-        b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
-        b.cursor = P<unsigned long long>(h->d_lcursor);
-        b.capacity = h->list_cap;
-        b.boff = P<uint32_t>(h->d_boff);
-        b.cnt = P<uint32_t>(h->d_cnt);
-        b.overflow = P<int>(h->d_flag) + 1;
-        b.fix = P<int2>(h->d_fix);
-        b.nfix = P<int>(h->d_flag) + 2;
-        b.vol = P<double>(h->d_vol);
-        b.inv_vst = (float)h->inv_vst;
-        b.npmax = 2 * (int)h->runs.size();
-        b.uniform = h->uniform;
-        b.e0f = (float)h->edges[0];
-        b.inv_dr = h->inv_dr;
-        b.delta = h->delta;
-        b.inv_boxf = (float)(1.0 / h->g.box);
-        b.item_start = P<int>(h->d_istart);
-        b.item_cell = P<int>(h->d_icell);
-        b.slot_stretch = (double)h->npts >= 12.0 * (double)h->ncat * h->g.ncell ? 1 : 0;
-        {
-            // work items of the catalogues holding the chunk's primaries
-            int c0 = 0, c1 = 0;
-            while (c0 + 1 < h->ncat && h->pt_off[c0 + 1] <= ch.p_begin) ++c0;
-            c1 = c0;
-            while (c1 + 1 < h->ncat && h->pt_off[c1 + 1] < ch.p_end) ++c1;
-            b.item_lo = h->item_cat[c0];
-            b.item_hi = h->item_cat[c1 + 1];
-            if (ch.item_lo >= 0) {
-                b.item_lo = ch.item_lo;
-                b.item_hi = ch.item_hi;
-            }
+    HIPCHK(launch_fill_u64(P<unsigned long long>(h->d_lcursor), kSlots * 16, 0ull, h->stream));
+    HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 2, 1, 0, h->stream));  // fix-up list length
+    BinArgs b{};
+    b.pf = P<float4>(h->d_pf);
+    b.pd = P<double4>(h->d_pd);
+    b.catid = P<int>(h->d_catid);
+    b.cell_start = P<int>(h->d_start);
+    b.pt_off = P<int64_t>(h->d_pt_off);
+    b.runs = P<StencilRun>(h->d_runs);
+    b.nruns = (int)h->runs.size();
+    b.g = h->g;
+    b.nb = h->nb;
+    b.e2 = P<double>(h->d_e2);
+    b.e2f = P<float>(h->d_e2f);
+    b.guard = P<float>(h->d_guard);
+    b.p_begin = ch.p_begin;
+    b.p_end = ch.p_end;
+    b.list = h->fp64 ? P<uint32_t>(h->d_list) : nullptr;
+    b.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
+    // unit weights with the whole m range in one FP32 lane (lmax <= 10):
+    // the harmonic kernels that read the records (their UNIT forms) take
+    // no weight, so a record is (dx, dy, dz)
+    b.rec3 = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
+    b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
+    b.cursor = P<unsigned long long>(h->d_lcursor);
+    b.capacity = h->list_cap;
+    b.boff = P<uint32_t>(h->d_boff);
+    b.cnt = P<uint32_t>(h->d_cnt);
+    b.overflow = P<int>(h->d_flag) + 1;
+    b.fix = P<int2>(h->d_fix);
+    b.nfix = P<int>(h->d_flag) + 2;
+    b.nfix_total = P<int>(h->d_flag) + 3;
+    b.vol = P<double>(h->d_vol);
+    b.inv_vst = (float)h->inv_vst;
+    b.npmax = 2 * (int)h->runs.size();
+    b.uniform = h->uniform;
+    b.e0f = (float)h->edges[0];
+    b.inv_dr = h->inv_dr;
+    b.delta = h->delta;
+    b.inv_boxf = (float)(1.0 / h->g.box);
+    b.item_start = P<int>(h->d_istart);
+    b.item_cell = P<int>(h->d_icell);
+    b.slot_stretch = (double)h->npts >= 12.0 * (double)h->ncat * h->g.ncell ? 1 : 0;
+    {
+        // work items of the catalogues holding the chunk's primaries
+        int c0 = 0, c1 = 0;
+        while (c0 + 1 < h->ncat && h->pt_off[c0 + 1] <= ch.p_begin) ++c0;
+        c1 = c0;
+        while (c1 + 1 < h->ncat && h->pt_off[c1 + 1] < ch.p_end) ++c1;
+        b.item_lo = h->item_cat[c0];
+        b.item_hi = h->item_cat[c1 + 1];
+        if (ch.item_lo >= 0) {
+            b.item_lo = ch.item_lo;
+            b.item_hi = ch.item_hi;
         }
-        Timer t;
-        t_begin(h, 1, t);
-        HIPCHK(launch_pair_bin(b, h->stream));
-        t_end(h, t);
-        int flag[2] = {0, 0};
-        HIPCHK(hipMemcpyAsync(flag, P<int>(h->d_flag) + 1, sizeof(flag), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        if (!flag[0] && flag[1] > 0) {
-            // primaries whose predicted bin regions overflowed: exact counts
-            b.nfix_items = flag[1];
-            h->nfix_total += flag[1];
-            Timer tf;
-            t_begin(h, 1, tf);
-            HIPCHK(launch_pair_fix(b, h->stream));
-            t_end(h, tf);
-            HIPCHK(hipMemcpyAsync(flag, P<int>(h->d_flag) + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
-        }
-        if (!flag[0]) break;
-        if (attempt == 5) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
-        unsigned long long ncap = std::min<unsigned long long>(4000000000ull, h->list_cap * 2);
-        if (ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
-        h->list_cap = ncap;
-        if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
     }
+    Timer tb;
+    t_begin(h, 1, tb);
+    HIPCHK(launch_pair_bin(b, h->stream));
+    // primaries whose predicted bin regions overflowed: exact counts
+    HIPCHK(launch_pair_fix(b, h->stream));
+    t_end(h, tb);
     AlmArgs a{};
     a.pf = P<float4>(h->d_pf);
     a.pa = P<float4>(h->d_pa);
@@ -949,14 +935,29 @@ tpcf_status check_nonfinite(tpcf_handle h) {
 }
 
 // pair pass over every chunk; contracts each chunk right away when the
-// operand cannot be kept for the whole group
+// operand cannot be kept for the whole group. The chunks run without a host
+// round trip; the list-overflow flag and the fix-up count are read once at
+// the end, and a pass whose lists ran out of room is run again with twice the
+// room (its partial sums are overwritten, not accumulated).
 tpcf_status pair_pass(tpcf_handle h, bool contract_now) {
     tpcf_status st;
-    for (const Chunk& ch : h->chunks) {
-        if ((st = pair_chunk(h, ch)) != TPCF_OK) return st;
-        if (contract_now && (st = contract_chunk(h, ch)) != TPCF_OK) return st;
+    for (int attempt = 0;; ++attempt) {
+        HIPCHK(launch_fill_i32(P<int>(h->d_flag) + 1, 3, 0, h->stream));  // overflow, fix-up length and total
+        for (const Chunk& ch : h->chunks) {
+            if ((st = pair_chunk(h, ch)) != TPCF_OK) return st;
+            if (contract_now && (st = contract_chunk(h, ch)) != TPCF_OK) return st;
+        }
+        int flag[3] = {0, 0, 0};
+        HIPCHK(hipMemcpyAsync(flag, P<int>(h->d_flag) + 1, sizeof(flag), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->nfix_total += flag[2];
+        if (!flag[0]) return TPCF_OK;
+        const unsigned long long ncap = std::min<unsigned long long>(4000000000ull, h->list_cap * 2);
+        if (attempt == 5 || ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
+        h->list_cap = ncap;
+        h->list_grow = std::min(h->list_grow * 2.0, 64.0);  // kept for the next groups and calls
+        if ((st = ensure(h, h->d_list, (size_t)list_elem_bytes(h) * h->list_cap)) != TPCF_OK) return st;
     }
-    return TPCF_OK;
 }
 
 // Polar part of Y_lm for any sign of m: Y_lm = Theta_lm(cos t) e^{i m phi},

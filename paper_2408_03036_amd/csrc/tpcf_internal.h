@@ -97,7 +97,7 @@ struct BinArgs {
     int* overflow;           // [1] set when `list` is too small
     int2* fix;               // fix-up list: (cell, chunk-relative primary) whose predicted bin regions overflowed
     int* nfix;               // [1] its length
-    int64_t nfix_items;      // length of the list processed by a fix-up launch
+    int* nfix_total;         // [1] the fix-up launches add the lengths they processed
     const double* vol;       // [nb] shell volumes
     float inv_vst;           // 1 / stencil volume (the box in one-cell mode)
     int npmax;               // capacity of the piece table (>= 2 nruns)
@@ -112,6 +112,9 @@ struct BinArgs {
 };
 constexpr int kSlots = 256;  // list allocation cursors (each on its own 128-byte line)
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);
+// Fix-up launch: a fixed grid walks the list whose length the binning launch
+// left at *nfix, so the two launches need no host round trip between them.
+constexpr int kFixGrid = 2048;
 hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s);
 size_t pair_bin_lds_bytes(int npmax);
 

@@ -398,49 +398,11 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
 //     primary with more hits in some bin than its region holds is appended to
 //     the fix-up list instead of being published.
 //   FIX = true: two sweeps with exact counts (count, allocate, write).
+// bin_item takes the primaries first .. last - 1 of home cell gc; every
+// thread of the workgroup calls it with the same item.
 template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
-__global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
-    extern __shared__ unsigned char smem[];
-    BinTables& T = *reinterpret_cast<BinTables*>(smem);
-    for (int i = threadIdx.x; i <= a.nb; i += blockDim.x) {
-        T.e2[i] = a.e2[i];
-        T.e2f[i] = a.e2f[i];
-        T.guard[i] = a.guard[i];
-    }
-    size_t off = (sizeof(BinTables) + 15) / 16 * 16;
-    float4* tiles = reinterpret_cast<float4*>(smem + off);
-    off += sizeof(float4) * 2 * kTile;
-    uint32_t* tent = reinterpret_cast<uint32_t*>(smem + off);
-    off += sizeof(uint32_t) * 2 * kTile;
-    Pieces S = pieces_view(smem + off, a.npmax);
-    off += pieces_lds_bytes(a.npmax);
-    ItemCtx c;
-    c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    c.lane = lane_id();
-    c.cnt = reinterpret_cast<uint32_t*>(smem + off) + c.wave * (kGM * kMaxBins);
-    c.T = &T;
-    c.S = &S;
-    c.tiles = tiles;
-    c.tent = tent;
-    c.capoff = T.capoff;
-
-    int gc;
-    int64_t first, last;
-    int64_t item;
-    if constexpr (FIX) {
-        item = xcd_block(blockIdx.x, (int64_t)gridDim.x);
-        if (item >= a.nfix_items) return;
-        const int2 f = a.fix[item];
-        gc = f.x;
-        first = a.p_begin + f.y;
-        last = first + 1;
-    } else {
-        item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
-        if (item >= a.item_hi) return;
-        gc = a.item_cell[item];
-        first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
-        last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
-    }
+__device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S, BinTables& T, int gc,
+                                         int64_t first, int64_t last) {
     // The region follows the wavefront's first primary pl0 (chunk-relative),
     // which spreads evenly when cells are small (items rarely full). With
     // full items of 16 primaries (large cells) that would use only a quarter
@@ -553,6 +515,54 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
                 a.boff[pl * a.nb + lane] = pub ? base[g] + co : 0u;
             }
         }
+    }
+}
+
+// The binning launch: one workgroup per work item, or (FIX) a fixed grid
+// whose workgroups take the fix-up list's primaries in turn.
+template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
+__global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
+    extern __shared__ unsigned char smem[];
+    BinTables& T = *reinterpret_cast<BinTables*>(smem);
+    for (int i = threadIdx.x; i <= a.nb; i += blockDim.x) {
+        T.e2[i] = a.e2[i];
+        T.e2f[i] = a.e2f[i];
+        T.guard[i] = a.guard[i];
+    }
+    size_t off = (sizeof(BinTables) + 15) / 16 * 16;
+    float4* tiles = reinterpret_cast<float4*>(smem + off);
+    off += sizeof(float4) * 2 * kTile;
+    uint32_t* tent = reinterpret_cast<uint32_t*>(smem + off);
+    off += sizeof(uint32_t) * 2 * kTile;
+    Pieces S = pieces_view(smem + off, a.npmax);
+    off += pieces_lds_bytes(a.npmax);
+    ItemCtx c;
+    c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    c.lane = lane_id();
+    c.cnt = reinterpret_cast<uint32_t*>(smem + off) + c.wave * (kGM * kMaxBins);
+    c.T = &T;
+    c.S = &S;
+    c.tiles = tiles;
+    c.tent = tent;
+    c.capoff = T.capoff;
+
+    if constexpr (FIX) {
+        // the fix-up list the binning launch left on the device, walked by a
+        // fixed grid (no host round trip between the two launches)
+        const int nfix = *a.nfix;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.nfix_total, nfix);
+        for (int64_t item = blockIdx.x; item < nfix; item += gridDim.x) {
+            const int2 f = a.fix[item];
+            __syncthreads();  // the previous item's pieces and tiles are no longer read
+            bin_item<SINGLE, UNIFORM, REC, true>(a, c, S, T, f.x, a.p_begin + f.y, a.p_begin + f.y + 1);
+        }
+    } else {
+        const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
+        if (item >= a.item_hi) return;
+        const int gc = a.item_cell[item];
+        const int64_t first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
+        const int64_t last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
+        bin_item<SINGLE, UNIFORM, REC, false>(a, c, S, T, gc, first, last);
     }
 }
 
@@ -1128,8 +1138,9 @@ hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s) {
-    if (a.p_end <= a.p_begin || a.nfix_items <= 0) return hipSuccess;
-    const int64_t nblk = (a.nfix_items + 7) / 8 * 8;
+    if (a.p_end <= a.p_begin) return hipSuccess;
+    // the list's length is read on the device: a fixed grid of 8 workgroups per CU
+    const int64_t nblk = kFixGrid;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
     return a.rec ? launch_bin_rec<true, true>(a, s, nblk, lds) : launch_bin_rec<false, true>(a, s, nblk, lds);
 }

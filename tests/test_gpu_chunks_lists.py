@@ -40,16 +40,21 @@ def torch():
 
 
 def run_steps(torch, P, box, edges, lmax, mults, prec, limit=0, W=None, n_data=None):
-    """Steps 1-4 on one handle; returns (multipoles, pair count, harmonic-pass launches)."""
+    """Steps 1-4 twice on one handle; returns (multipoles, pair count,
+    harmonic-pass launches) of the second run. The first run settles the
+    list room: a clustered catalogue can overflow the room predicted from its
+    mean density, and the pass is then run again with more room, which the
+    handle keeps."""
     h = T.Handle(box, edges, lmax, precision=prec, workspace_limit=limit)
     h.set_timing(True)
-    h.build_grid(P, W, n_data)
-    h.alm_accumulate()
-    h.contract()
-    out = h.multipoles(mults)
-    h.sync()
-    n = h.pair_count()
-    _, launches = h.stage_times()
+    for rep in range(2):
+        h.build_grid(P, W, n_data)
+        h.alm_accumulate()
+        h.contract()
+        out = h.multipoles(mults)
+        h.sync()
+        n = h.pair_count()
+        _, launches = h.stage_times()
     h.close()
     return out.cpu().numpy(), n, int(launches[2])
 

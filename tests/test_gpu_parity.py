@@ -317,6 +317,32 @@ def test_batched_equals_single_bitwise(torch, prec):
 
 
 @pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
+def test_list_room_exhausted_pass_redone(torch, prec):
+    """Half of the points in one tight clump: their pairs exceed the list room
+    sized from the mean density several times over, so the pair pass runs out
+    of room, which it learns only after its last chunk, and is run again with
+    more room. The result still matches the oracle, and the pair count is
+    exact."""
+    box, edges, lmax = 100.0, np.array([1.0, 4.0, 7.0, 10.0]), 2
+    rng = np.random.default_rng(C.catalogue_seed(11))
+    clump = np.mod(50.0 + rng.normal(0.0, 1.2, size=(2000, 3)), box)
+    pos = np.vstack([C.poisson(2000, box, C.catalogue_seed(12)), clump])
+    mults = O.all_multipoles(lmax, 2)
+    ref, _, res = O.run(pos, box, edges, lmax, mults)
+    # the list room of the first pass: 1.15 (64 + sum_b 1.15 pred_b + 4 sqrt(pred_b) + 9)
+    # entries per primary (pred_b the mean-density count of bin b), at least 1e6
+    n = pos.shape[0]
+    pred = n / box ** 3 * 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    room = max(1e6, 1.15 * n * (64.0 + np.sum(1.15 * pred + 4.0 * np.sqrt(pred) + 9.0)))
+    assert res.npairs > 2.0 * room
+    got, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec)
+    say(f"  lists exhausted {PNAME[prec]}: {npairs} pairs against room for {room:.0f}, "
+        f"rel err {rel_err(got, ref):.3e}")
+    assert npairs == res.npairs
+    assert rel_err(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
 def test_crowded_cluster_exact_rebinning(torch, prec):
     """A dense clump inside a sparse box: its members see far more close
     neighbours than their cell's stencil predicts, so they take the exact
