@@ -142,6 +142,11 @@ tpcf_status tpcf_build_grid(tpcf_handle h, const double* d_pos, const double* d_
  * Step 2 -- pair pass: for every primary, every neighbour in the shells;
  * accumulates a_lm(p, b) (eq. (alm)) and the degenerate-triangle moments
  * sum_j w_j^2 P_L(cos theta_pj), L <= 2 lmax. Requires tpcf_build_grid.
+ * The chunks of primaries run without host round trips; the call waits for
+ * the stream once, after the last chunk, to learn whether the hit lists ran
+ * out of room (strong clustering), and then runs the pass again with twice
+ * the room (which the handle keeps for later calls). TPCF_ERR_ALLOC when the
+ * room cannot grow within the workspace limit or 4e9 entries.
  */
 tpcf_status tpcf_alm_accumulate(tpcf_handle h);
 
