@@ -610,14 +610,13 @@ tpcf_status plan_chunks(tpcf_handle h) {
     // room for the predicted bin regions of a primary of the densest
     // catalogue (the binning kernel's margin), plus the rare exact rebins (a
     // pass that runs out of room runs again with twice the room, and the
-    // handle keeps the factor for its later passes)
+    // handle keeps the factor for the list room of its later passes)
     const double lelem = list_elem_bytes(h);
     double hits_room = 64.0;
     for (int b = 0; b < h->nb; ++b) {
         const double pred = std::min((double)maxn, maxn / L3 * h->vol[b]);
         hits_room += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
     }
-    hits_room *= h->list_grow;  // room earlier passes of this handle were found to need
     const double list_per = lelem * hits_room;
     h->hits_per_list = hits / h->nb;
     int64_t budget = h->limit / 2;
@@ -673,7 +672,9 @@ tpcf_status plan_chunks(tpcf_handle h) {
     h->ldA = (maxch + 63) / 64 * 64;
     // 15 % above the predicted room: a catalogue of even density fills its
     // regions to their prediction on average, and the 256 regions differ
-    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, 1.15 * (double)maxch * hits_room));
+    // times the growth earlier passes of this handle needed (strong
+    // clustering); the chunk sizes keep the prediction
+    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, 1.15 * (double)maxch * hits_room * h->list_grow));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
