@@ -112,7 +112,7 @@ struct Staged {
     bool ok;
 };
 
-template <bool SINGLE, bool REC>
+template <bool SINGLE, int REC>
 __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, int total, int g,
                                            const float4* pf, const float* pw) {
     st.ok = g < total;
@@ -129,7 +129,7 @@ __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, 
         st.q = pf[st.j];
         // unit weights are applied when the candidate is stored: the weight
         // register is only ever written by its load
-        if (REC && pw) st.w = pw[st.j];
+        if (REC == 4 && pw) st.w = pw[st.j];
     }
 }
 
@@ -138,10 +138,10 @@ __device__ __forceinline__ void stage_load(Staged& st, const Pieces& S, int np, 
 // for an empty slot (past the last candidate, never tested): the write is
 // then harmless, and being unconditional it keeps the wait for the slot's
 // load on every path.
-template <bool SINGLE, bool REC>
+template <bool SINGLE, int REC>
 __device__ __forceinline__ void stage_store(const Staged& st, float4* dst, uint32_t* dent, uint32_t cst,
                                             int cshift, float hf, bool weighted) {
-    const float w = REC ? (weighted ? st.w : 1.f) : 0.f;
+    const float w = REC == 4 ? (weighted ? st.w : 1.f) : 0.f;
     float4 v;
     uint32_t e;
     if constexpr (SINGLE) {
@@ -190,10 +190,11 @@ __device__ __forceinline__ void separation(const BinArgs& a, const float4 q, flo
 }
 
 // Records a hit of primary g in bin b (b < 0: none): SWEEP 0 counts it;
-// SWEEP 1 and 2 take the next slot of the bin and write the list entry, or
-// with REC the record (dx, dy, dz, w_j); SWEEP 2 drops (but still counts) a
-// hit beyond the end of the bin's predicted region.
-template <int SWEEP, bool REC>
+// SWEEP 1 and 2 take the next slot of the bin and write what REC selects:
+// 0 the list entry (FP64 path), 3 the record (dx, dy, dz), 4 the record
+// (dx, dy, dz, w_j); SWEEP 2 drops (but still counts) a hit beyond the end of
+// the bin's predicted region.
+template <int SWEEP, int REC>
 __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int g, int b, uint32_t base_g,
                                         float dx, float dy, float dz, float w, uint32_t entry) {
     if constexpr (SWEEP == 0) {
@@ -203,12 +204,11 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
         // the lists are the same on every run
         const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
         if (SWEEP == 2 && pos >= c.capoff[b + 1]) return;
-        if constexpr (REC) {
-            if (a.rec3)
-                *reinterpret_cast<float3*>(reinterpret_cast<float*>(a.rec) + 3 * (size_t)(base_g + pos)) =
-                    make_float3(dx, dy, dz);
-            else
-                a.rec[base_g + pos] = make_float4(dx, dy, dz, w);
+        if constexpr (REC == 3) {
+            *reinterpret_cast<float3*>(reinterpret_cast<float*>(a.rec) + 3 * (size_t)(base_g + pos)) =
+                make_float3(dx, dy, dz);
+        } else if constexpr (REC == 4) {
+            a.rec[base_g + pos] = make_float4(dx, dy, dz, w);
         } else {
             a.list[base_g + pos] = entry;
         }
@@ -219,8 +219,8 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
 // (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
 // bin), the offsets having been prepared in cnt; SWEEP 2 does the same inside
 // the predicted bin regions capoff, and drops (but still counts) the hits
-// beyond a region's end. A hit is written as a list entry, or with REC as the
-// record (dx, dy, dz, w_j) that the FP32 harmonic pass streams.
+// beyond a region's end. A hit is written as a list entry, or (REC 3 or 4) as
+// the record that the FP32 harmonic pass streams.
 //
 // Each thread stages one slot of the next tile: its load is issued before the
 // tests and its LDS write follows them, so the tile's loads are covered by
@@ -230,7 +230,7 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
 // A pair inside the guard band of an edge is only marked during the tests
 // (one bit per (tile slot, primary) of the lane) and binned exactly after
 // them, outside the test loop.
-template <int SWEEP, bool SINGLE, bool UNIFORM, bool REC>
+template <int SWEEP, bool SINGLE, bool UNIFORM, int REC>
 __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, const float (&px)[kGM],
                                           const float (&py)[kGM], const float (&pz)[kGM],
                                           const uint32_t (&base)[kGM]) {
@@ -400,7 +400,7 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
 //   FIX = true: two sweeps with exact counts (count, allocate, write).
 // bin_item takes the primaries first .. last - 1 of home cell gc; every
 // thread of the workgroup calls it with the same item.
-template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
+template <bool SINGLE, bool UNIFORM, int REC, bool FIX>
 __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S, BinTables& T, int gc,
                                          int64_t first, int64_t last) {
     // The region follows the wavefront's first primary pl0 (chunk-relative),
@@ -520,7 +520,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
 
 // The binning launch: one workgroup per work item, or (FIX) a fixed grid
 // whose workgroups take the fix-up list's primaries in turn.
-template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
+template <bool SINGLE, bool UNIFORM, int REC, bool FIX>
 __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     extern __shared__ unsigned char smem[];
     BinTables& T = *reinterpret_cast<BinTables*>(smem);
@@ -1110,7 +1110,7 @@ hipError_t launch_alm_lmax(const AlmArgs& a, int fp64, hipStream_t s) {
 
 }  // namespace
 
-template <bool SINGLE, bool UNIFORM, bool REC, bool FIX>
+template <bool SINGLE, bool UNIFORM, int REC, bool FIX>
 hipError_t launch_bin_variant(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
     const hipError_t e = allow_full_lds((const void*)k_pair_bin<SINGLE, UNIFORM, REC, FIX>);
     if (e != hipSuccess) return e;
@@ -1118,7 +1118,7 @@ hipError_t launch_bin_variant(const BinArgs& a, hipStream_t s, int64_t nblk, siz
     return hipGetLastError();
 }
 
-template <bool REC, bool FIX>
+template <int REC, bool FIX>
 hipError_t launch_bin_rec(const BinArgs& a, hipStream_t s, int64_t nblk, size_t lds) {
     if (a.g.single) {
         return a.uniform ? launch_bin_variant<true, true, REC, FIX>(a, s, nblk, lds)
@@ -1134,7 +1134,8 @@ hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
     // a multiple of 8 blocks, so that the XCD remap is a permutation
     const int64_t nblk = (nitems + 7) / 8 * 8;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
-    return a.rec ? launch_bin_rec<true, false>(a, s, nblk, lds) : launch_bin_rec<false, false>(a, s, nblk, lds);
+    if (!a.rec) return launch_bin_rec<0, false>(a, s, nblk, lds);
+    return a.rec3 ? launch_bin_rec<3, false>(a, s, nblk, lds) : launch_bin_rec<4, false>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s) {
@@ -1142,7 +1143,8 @@ hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s) {
     // the list's length is read on the device: a fixed grid of 8 workgroups per CU
     const int64_t nblk = kFixGrid;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
-    return a.rec ? launch_bin_rec<true, true>(a, s, nblk, lds) : launch_bin_rec<false, true>(a, s, nblk, lds);
+    if (!a.rec) return launch_bin_rec<0, true>(a, s, nblk, lds);
+    return a.rec3 ? launch_bin_rec<3, true>(a, s, nblk, lds) : launch_bin_rec<4, true>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {

@@ -11,9 +11,12 @@ of a slice of primaries is compared as well. The batch is also checked by
 properties that hold at any size: each catalogue of the batch equals the same
 catalogue run alone, bit for bit, and the mixed path agrees with the FP64 path
 within the split-BF16 tolerance. A data + 5x randoms catalogue with
-data-minus-randoms weights checks every precision against the FP64 path at
+data-minus-randoms weights checks the FP64 path against stored oracle
+multipoles, and every precision against the FP64 path at
 full size.
 """
+import importlib.util
+import os
 import sys
 
 import numpy as np
@@ -178,6 +181,36 @@ def test_data_minus_randoms_large(torch):
     err = float(np.abs(got[..., mask] - ref_alm[..., mask]).max() / np.abs(ref_alm[..., mask]).max())
     say(f"  weighted a_lm slice rel err {err:.3e}")
     assert err < 1e-5
+
+
+def test_c5_catalogue_fp64_matches_stored_oracle(torch):
+    """One catalogue of the large data + 5x randoms shape (10^5 clustered data
+    points, 5x10^5 randoms, weights 1 and -N_D/N_R, 1500 Mpc/h, 12 bins over
+    [10, 130], lmax 10, L <= 4): the FP64 path's multipoles, element by
+    element, against the oracle's, which take minutes and are stored by
+    tests/golden/make_c5_reference.py. The positions are regenerated with the
+    same numpy generator and checked against the stored SHA-256 first."""
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_c5_reference", os.path.join(golden, "make_c5_reference.py"))
+    G = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    ref = np.load(os.path.join(golden, "c5_catalogue_reference.npz"))
+    pos, w, nd = G.catalogue()
+    assert G.digest(pos) == str(ref["pos_sha256"]), "the generator no longer gives the stored catalogue"
+    mults = [tuple(int(v) for v in t) for t in ref["mults"]]
+    say(f"  C5 catalogue: {pos.shape[0]} points, {len(mults)} multipoles")
+    h = T.Handle(G.BOX, G.EDGES, G.LMAX, precision=T.PREC_FP64)
+    h.build_grid(torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda(), nd)
+    h.alm_accumulate()
+    h.contract()
+    got = h.multipoles(mults).cpu().numpy()
+    h.sync()
+    npairs = h.pair_count()
+    h.close()
+    assert npairs == int(ref["npairs"])
+    err = float(np.abs(got - ref["multipoles"]).max() / np.abs(ref["multipoles"]).max())
+    say(f"  C5 catalogue FP64 rel err vs stored oracle {err:.3e}")
+    assert err < 1e-12
 
 
 def test_batched_64_catalogues(torch):

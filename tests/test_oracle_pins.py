@@ -289,3 +289,26 @@ def test_poisson_null():
     expect[mults.index((0, 0, 0))] = 1.0
     z = np.abs(mean - expect) / np.maximum(sd, 1e-300)
     assert np.all(z < 5.0), float(z.max())
+
+
+# ------------------------------------------------------------------ stored references
+
+
+def test_c5_reference_catalogue_reproducible():
+    """The stored oracle multipoles of the large data + 5x randoms catalogue
+    (tests/golden/make_c5_reference.py) belong to the catalogue the seeded
+    numpy generator gives now: same SHA-256 of the positions, one multipole
+    row per stored triple, finite values."""
+    import importlib.util
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_c5_reference", os.path.join(golden, "make_c5_reference.py"))
+    G = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    ref = np.load(os.path.join(golden, "c5_catalogue_reference.npz"))
+    pos, w, nd = G.catalogue()
+    assert pos.shape == (6 * nd, 3) and w.shape == (6 * nd,)
+    assert G.digest(pos) == str(ref["pos_sha256"])
+    nb = len(G.EDGES) - 1
+    assert ref["multipoles"].shape == (len(ref["mults"]), nb, nb)
+    assert np.isfinite(ref["multipoles"]).all()
+    assert [tuple(t) for t in ref["mults"].tolist()] == [tuple(t) for t in O.all_multipoles(G.LMAX, G.LMAX_L)]
