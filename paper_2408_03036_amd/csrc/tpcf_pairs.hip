@@ -195,11 +195,11 @@ __device__ __forceinline__ void separation(const BinArgs& a, const float4 q, flo
 // (dx, dy, dz, w_j); SWEEP 2 drops (but still counts) a hit beyond the end of
 // the bin's predicted region.
 template <int SWEEP, int REC>
-__device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int g, int b, uint32_t base_g,
+__device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int g, bool hit, int b, uint32_t base_g,
                                         float dx, float dy, float dz, float w, uint32_t entry) {
     if constexpr (SWEEP == 0) {
-        if (b >= 0) atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
-    } else if (b >= 0 && base_g != kNoBase) {
+        if (hit) atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
+    } else if (hit && base_g != kNoBase) {
         // the LDS unit serves the lanes of one atomic in a fixed order, so
         // the lists are the same on every run
         const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
@@ -299,11 +299,9 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
                         }
                     }
                 }
-                const int b = (valid && !near && (unsigned)bb < nbu) ? bb : -1;
-                if (__ballot(valid && near) != 0ull) {
-                    if (valid && near) nearbits |= (NearMask)1 << (u * kGM + g);
-                }
-                put_hit<SWEEP, REC>(a, c, g, b, base[g], dx, dy, dz, q.w, entry);
+                const bool hit = valid && !near && (unsigned)bb < nbu;
+                nearbits |= (valid && near) ? (NearMask)1 << (u * kGM + g) : (NearMask)0;
+                put_hit<SWEEP, REC>(a, c, g, hit, bb, base[g], dx, dy, dz, q.w, entry);
             }
         }
         // the next tile's slot (written also after the last tile: the other
@@ -331,7 +329,7 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
                     separation<SINGLE>(a, q, px[g], py[g], pz[g], dx, dy, dz);
                     const int b = exact_pair<SINGLE>(a.pd, c.cs + c.wave + kNW * g, c.cstart, entry, c.mask,
                                                      c.cshift, c.cx, c.cy, c.cz, a.g.k, a.g.nc, a.g.box, a.nb, T.e2);
-                    put_hit<SWEEP, REC>(a, c, g, b, base[g], dx, dy, dz, q.w, entry);
+                    put_hit<SWEEP, REC>(a, c, g, b >= 0, b, base[g], dx, dy, dz, q.w, entry);
                 }
             }
         }
