@@ -268,7 +268,9 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
         }
         const int nt = min(kTile, c.total - t);
         NearMask nearbits = 0;
-#pragma unroll 2
+        // fully unrolled: every guard-band bit is a constant (66 VGPRs, seven
+        // waves per SIMD, measured faster than the loop unrolled twice)
+#pragma unroll
         for (int u = 0; u < kUT; ++u) {
             const int i = u * 64 + c.lane;
             const float4 q = cur[i];
