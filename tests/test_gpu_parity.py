@@ -454,6 +454,46 @@ def test_bad_catalogue_isolated_in_batch(torch, prec):
     h.close()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_degenerate_catalogues_alone_and_batched(torch, prec):
+    """Catalogues at the edge of the method: one point (no pair), points
+    farther apart than the last edge (no pair in any shell), and an
+    equilateral triangle inside one bin (every ordered distinct triplet in
+    that bin, 6 of them), each alone and together with a normal catalogue in
+    one ragged batch. Pair counts are exact, the multipoles equal the oracle's
+    (zero where there is no pair), and the batched results equal the single
+    runs bit for bit."""
+    box, edges, lmax = 100.0, np.array([2.0, 4.0, 6.0, 8.0]), 2
+    mults = O.all_multipoles(lmax, 2)
+    one = np.array([[10.0, 20.0, 30.0]])
+    apart = np.array([[5.0, 5.0, 5.0], [30.0, 5.0, 5.0], [5.0, 60.0, 5.0], [70.0, 70.0, 70.0]])
+    tri = 50.0 + np.array([[0.0, 0.0, 0.0], [5.0, 0.0, 0.0], [2.5, 5.0 * np.sqrt(3.0) / 2.0, 1.0]])
+    normal = C.zeldovich(800, box, 2.0, 0.8, 191, grid=16)
+    cats = [one, apart, tri, normal]
+    nd = [3, 4, 3, 800]  # n_data >= 3 for RRR
+    singles, counts = [], []
+    for cat, n_data in zip(cats, nd):
+        ref, _, res = O.run(cat, box, edges, lmax, mults, n_data=n_data)
+        got, npairs, _, _ = run_gpu(torch, cat, box, edges, lmax, mults, prec, n_data=n_data)
+        assert npairs == res.npairs
+        counts.append(npairs)
+        if res.npairs == 0:
+            assert not np.any(got) and not np.any(ref)
+        else:
+            assert rel_err(got, ref) < TOL[prec]
+        singles.append(got)
+    # the triangle: 3 x 2 ordered distinct pairs, all in the middle bin
+    assert O.estimate(tri, box, edges, 0).npairs == 6
+    h = T.Handle(box, edges, lmax, precision=prec)
+    out = h.run_catalogs([c.shape[0] for c in cats], nd, gpu(torch, np.vstack(cats)), None, mults)
+    h.sync()
+    h.close()
+    batched = out.cpu().numpy()
+    for i in range(len(cats)):
+        assert np.array_equal(batched[i], singles[i]), i
+    say(f"  degenerate catalogues {PNAME[prec]}: pairs {counts}, batched == single")
+
+
 def test_out_of_order_calls(torch):
     h = T.Handle(50.0, np.array([1.0, 5.0]), 2)
     with pytest.raises(T.TpcfError) as e:
