@@ -259,9 +259,11 @@ tpcf_status tpcf_autotune(tpcf_handle h, const double* d_pos, const double* d_w,
  *  list_mode:     harmonic pass: 0 one lane per (primary, bin) list, 1 one
  *                 wavefront per list (FP32 paths with lmax <= 6; elsewhere
  *                 the lane kernel runs), -1 = by the predicted list length.
- *  contract_step: primaries per step of the split-BF16 contraction: 16, 32,
- *                 64 or 128 (the longest that fits when that is shorter), or
- *                 0 = the longest that fits. Other precisions ignore it.
+ *  contract_step: longest step (primaries) of the split-BF16 contraction:
+ *                 16, 32, 64 or 128, or 0 = up to 512. Each m takes the
+ *                 longest step up to this that its columns' staging fits
+ *                 (the narrow high-m operands take the longest). Other
+ *                 precisions ignore it.
  *  ms:            (tpcf_autotune_plan) the timed pair pass and contraction of
  *                 the sample with this plan, in ms.
  */

@@ -596,6 +596,24 @@ constexpr int kBfTPW = 2;
 // (the weighted staging also holds the weights)
 template <bool W> constexpr int bf_ipt() { return W ? 2 : 4; }
 
+// Step length (primaries) of each m, passed by value to the kernel.
+struct BfSteps { int ks[kMaxLmax + 1]; };
+
+// Step length of one m: the longest power of two from cap down to 16 whose
+// staging fits the threads' registers (ncol * KS / 8 items of 8 primaries,
+// ipt per thread) and whose nbuf LDS buffers fit in lds bytes; 0 if none.
+// The narrow high-m operands thus take long steps: a workgroup's time goes
+// with its number of steps (each waits for its loads and a barrier), not
+// with its bytes.
+inline int bf_step(int ncol, int nplanes, int ipt, int nbuf, int cap, size_t lds) {
+    for (int ks = cap; ks >= 16; ks /= 2) {
+        if ((int64_t)ncol * (ks / 8) > (int64_t)64 * kBfWaves * ipt) continue;
+        if ((size_t)nbuf * nplanes * ncol * (ks + 8) * sizeof(uint16_t) > lds) continue;
+        return ks;
+    }
+    return 0;
+}
+
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
 __device__ inline uint32_t cvt_pk_bf16(float a, float b) {
@@ -628,7 +646,7 @@ struct BfStage {
 };
 
 template <int NPC, bool W>
-__global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a, int KS, int nbuf) {
+__global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a, BfSteps steps, int nbuf) {
     constexpr int TS = 32;
     extern __shared__ unsigned char smem[];
     const int s = blockIdx.x;
@@ -647,10 +665,11 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     const int lane = threadIdx.x & 63;
     const int64_t pa = a.sub_start[s], pb = a.sub_start[s + 1];
     const int ncol = nt * TS;
-    const int KSP = KS + 8;
     constexpr bool weighted = W;
     constexpr int IPT = bf_ipt<W>();
     const int nplanes = weighted ? 2 * NPC : NPC;
+    const int KS = steps.ks[m];
+    const int KSP = KS + 8;
     const int plane = ncol * KSP;                 // elements per plane
     const int bufsz = nplanes * plane;            // elements per buffer
     uint16_t* lds = reinterpret_cast<uint16_t*>(smem);
@@ -754,41 +773,59 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
         }
     };
 
+    // FP32 accumulation spans at most 128 primaries of one part, or one step
+    // of both parts where a step is shorter: then the sums go to FP64
+    auto flush = [&]() {
+#pragma unroll
+        for (int q = 0; q < kBfTPW; ++q) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) accd[q][r] += (double)acc32[q][r];
+            acc32[q] = (f32x16)0.0f;
+        }
+    };
     const int i = lane & 31, kg = lane >> 5;
-    // MFMAs of step st from LDS buffer buf, then the FP64 flush after the last part
+    // MFMAs of NQ valid tiles over one step: no branch inside, so that the
+    // LDS reads of one tile or slice overlap the MFMAs of the previous one
+    auto mma = [&](auto nq, const uint16_t* xp, const uint16_t* wp) {
+        constexpr int NQ = decltype(nq)::value;
+        int ra[NQ], rb[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            ra[q] = (ti[q] * TS + i) * KSP + 8 * kg;
+            rb[q] = (tj[q] * TS + i) * KSP + 8 * kg;
+        }
+        const int kc = KS > 128 ? 128 : KS;
+        for (int kb = 0; kb < KS; kb += kc) {
+#pragma unroll 2
+            for (int k0 = kb; k0 < kb + kc; k0 += 16) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    bf16x8 ap[NPC], bp[NPC];
+#pragma unroll
+                    for (int u = 0; u < NPC; ++u) {
+                        ap[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wp + u * plane + ra[q] + k0));
+                        bp[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(xp + u * plane + rb[q] + k0));
+                    }
+                    // products of pieces u, v with u + v <= NPC - 1
+#pragma unroll
+                    for (int u = 0; u < NPC; ++u)
+#pragma unroll
+                        for (int v2 = 0; v2 < NPC; ++v2)
+                            if (u + v2 <= NPC - 1)
+                                acc32[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[u], bp[v2], acc32[q], 0, 0, 0);
+                }
+            }
+            if (KS > 128) flush();
+        }
+    };
+    // MFMAs of step st from LDS buffer buf, then the FP64 flushes (a second
+    // tile of a wave is valid only if its first is)
     auto compute = [&](int st, int buf) {
         const uint16_t* xp = lds + buf * bufsz;
         const uint16_t* wp = weighted ? xp + NPC * plane : xp;
-        for (int k0 = 0; k0 < KS; k0 += 16) {
-#pragma unroll
-            for (int q = 0; q < kBfTPW; ++q) {
-                if (!tv[q]) continue;
-                const int ra = (ti[q] * TS + i) * KSP + k0 + 8 * kg;
-                const int rb = (tj[q] * TS + i) * KSP + k0 + 8 * kg;
-                bf16x8 ap[NPC], bp[NPC];
-#pragma unroll
-                for (int u = 0; u < NPC; ++u) {
-                    ap[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wp + u * plane + ra));
-                    bp[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(xp + u * plane + rb));
-                }
-                // products of pieces u, v with u + v <= NPC - 1
-#pragma unroll
-                for (int u = 0; u < NPC; ++u)
-#pragma unroll
-                    for (int v2 = 0; v2 < NPC; ++v2)
-                        if (u + v2 <= NPC - 1)
-                            acc32[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[u], bp[v2], acc32[q], 0, 0, 0);
-            }
-        }
-        if (st % parts == parts - 1) {
-            // FP32 accumulation never spans more than one step of KS primaries
-#pragma unroll
-            for (int q = 0; q < kBfTPW; ++q) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) accd[q][r] += (double)acc32[q][r];
-                acc32[q] = (f32x16)0.0f;
-            }
-        }
+        if (tv[1]) mma(std::integral_constant<int, 2>{}, xp, wp);
+        else if (tv[0]) mma(std::integral_constant<int, 1>{}, xp, wp);
+        if (KS <= 128 && st % parts == parts - 1) flush();
     };
 
     if (nbuf == 2) {
@@ -1103,21 +1140,34 @@ hipError_t launch_contract_mode(const ContractArgs& a, hipStream_t s) {
 
 }  // namespace
 
-// Step length and buffer count of the split-BF16 contraction: the longest
-// step (128, 64, 32 or 16 primaries, at most ks_max when given) whose staging
-// fits the per-thread registers, double-buffered when both buffers fit in LDS.
-struct BfPlan { int KS, nbuf; size_t lds; };
-BfPlan bf_plan(int npc, int ncol, bool weighted, int ks_max = 0) {
+// Step cap and buffer count of the split-BF16 contraction. Every m takes
+// its own step (bf_step): the longest up to cap (512, or ks_max when given)
+// that fits the registers and LDS for its columns; m = 0, the widest, needs
+// at least 16. Double-buffered when every m's buffers fit in LDS. lds is the
+// largest need over the m (the allocation of each workgroup).
+struct BfPlan { BfSteps steps; int nbuf; size_t lds; };
+BfPlan bf_plan(int npc, int nb, int lmax, bool weighted, int ks_max = 0) {
     const int nplanes = weighted ? 2 * npc : npc;
     const int ipt = weighted ? bf_ipt<true>() : bf_ipt<false>();
-    const int top = ks_max >= 16 ? std::min(ks_max, 128) : 128;
-    for (int nbuf = 2; nbuf >= 1; --nbuf)
-        for (int KS = top; KS >= 16; KS /= 2) {
-            if ((size_t)ncol * (KS / 8) > (size_t)64 * kBfWaves * ipt) continue;
-            const size_t lds = (size_t)nbuf * nplanes * ncol * (KS + 8) * sizeof(uint16_t);
-            if (lds <= 160 * 1024) return {KS, nbuf, lds};
+    const int cap = ks_max >= 16 ? std::min(ks_max, 512) : 512;
+    BfPlan pl{};
+    for (int nbuf = 2; nbuf >= 1; --nbuf) {
+        size_t need = 0;
+        bool ok = lmax <= kMaxLmax;
+        for (int m = 0; m <= lmax && ok; ++m) {
+            const int ncol = (nb * (lmax - m + 1) + 31) / 32 * 32;
+            const int ks = bf_step(ncol, nplanes, ipt, nbuf, cap, 160 * 1024);
+            ok = ks > 0;
+            pl.steps.ks[m] = ks;
+            need = std::max(need, (size_t)nbuf * nplanes * ncol * (ks + 8) * sizeof(uint16_t));
         }
-    return {0, 0, 0};
+        if (ok) {
+            pl.nbuf = nbuf;
+            pl.lds = need;
+            return pl;
+        }
+    }
+    return BfPlan{};
 }
 
 template <int NPC, bool W>
@@ -1126,12 +1176,12 @@ hipError_t launch_contract_bf16_w(const ContractArgs& a, hipStream_t s) {
     const int nt0 = (K0 + 31) / 32;
     const int ntiles0 = nt0 * (nt0 + 1) / 2;
     const int ngroups = (ntiles0 + kBfWaves * kBfTPW - 1) / (kBfWaves * kBfTPW);
-    const BfPlan pl = bf_plan(NPC, nt0 * 32, !a.unit_weights, a.ks_max);
-    if (pl.KS == 0) return hipErrorInvalidValue;
+    const BfPlan pl = bf_plan(NPC, a.nb, a.lmax, !a.unit_weights, a.ks_max);
+    if (pl.nbuf == 0) return hipErrorInvalidValue;
     const hipError_t e = allow_full_lds((const void*)k_contract_bf16<NPC, W>);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_contract_bf16<NPC, W>), dim3(a.nsub, a.lmax + 1, ngroups), dim3(64 * kBfWaves),
-                       pl.lds, s, a, pl.KS, pl.nbuf);
+                       pl.lds, s, a, pl.steps, pl.nbuf);
     return hipGetLastError();
 }
 
@@ -1166,8 +1216,7 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t s) {
             // a split-BF16 step must stage at least 16 primaries of every
             // column in the threads' registers (nbins (lmax + 1) <= 512 with
             // weights); beyond that the FP32 MFMA contraction runs instead
-            const int K0 = a.nb * (a.lmax + 1);
-            if (bf_plan(a.mode == 2 ? 2 : 3, (K0 + 31) / 32 * 32, !a.unit_weights, a.ks_max).KS == 0)
+            if (bf_plan(a.mode == 2 ? 2 : 3, a.nb, a.lmax, !a.unit_weights, a.ks_max).nbuf == 0)
                 return launch_contract_mode<1>(a, s);
             return a.mode == 2 ? launch_contract_bf16<2>(a, s) : launch_contract_bf16<3>(a, s);
         }
@@ -1181,8 +1230,8 @@ size_t contract_lds_bytes(int mode, int nb, int lmax) {
         case 0: return contract_lds<0>((K0 + 15) / 16 * 16);
         case 1: return contract_lds<1>((K0 + 31) / 32 * 32);
         default: {
-            const BfPlan pl = bf_plan(mode == 2 ? 2 : 3, (K0 + 31) / 32 * 32, true);
-            return pl.KS ? pl.lds : contract_lds<1>((K0 + 31) / 32 * 32);
+            const BfPlan pl = bf_plan(mode == 2 ? 2 : 3, nb, lmax, true);
+            return pl.nbuf ? pl.lds : contract_lds<1>((K0 + 31) / 32 * 32);
         }
     }
 }
