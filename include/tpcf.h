@@ -163,7 +163,10 @@ tpcf_status tpcf_get_alm(tpcf_handle h, int64_t first, int64_t count, double* d_
  * real part (the imaginary part does not enter any even-parity multipole),
  * degenerate triangles removed unless TPCF_F_KEEP_DEGENERATE.
  * d_nnn_out: NULL, or (lmax+1)^3 x nbins x nbins float64 laid out
- * [m][l1][l2][b1][b2] (entries with l1 < m or l2 < m are zero).
+ * [m][l1][l2][b1][b2] (entries with l1 < m or l2 < m are zero); refused
+ * with TPCF_ERR_STATE after a tpcf_run_catalogs that stopped the self
+ * moments, skipped blocks, or whose last group held several catalogues (the
+ * step calls give every catalogue's).
  * Requires step 2.
  */
 tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out);
@@ -173,7 +176,9 @@ tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out);
  *  h_l1l2L: host array n_mult x 3 of (l1, l2, L) with l1, l2 <= lmax,
  *           |l1 - l2| <= L <= l1 + l2 and l1 + l2 + L even (eq. (TripoSH)).
  *  d_out  : n_mult x nbins x nbins float64.
- * Requires step 3.
+ * Requires step 3, and a handle whose sums are those of one catalogue: after
+ * a tpcf_run_catalogs whose last group held several, TPCF_ERR_STATE (that
+ * call returns their multipoles).
  */
 tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2L,
                             double* d_out);
@@ -190,7 +195,11 @@ tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2
  * multipole being orthogonal over m); the results equal those of steps 1-4 bit
  * for bit. Until the next tpcf_build_grid the handle then refuses, with
  * TPCF_ERR_STATE, a tpcf_contract export of NNN^m and tpcf_multipoles triples
- * with L > lmax.
+ * with L > lmax. Likewise the split-BF16 contraction of such a run forms only
+ * the (l1, l2) blocks that its multipoles couple (|l1 - l2| up to the largest
+ * among them, each multipole needing |l1 - l2| <= L): until the next
+ * tpcf_build_grid, triples with a larger |l1 - l2| and the per-m export are
+ * refused with TPCF_ERR_STATE.
  * A catalogue with a non-finite coordinate does not stop the others: its
  * results are NaN, its status (tpcf_catalog_status) TPCF_ERR_DEVICE, the other
  * catalogues' results are complete and equal those of a batch without it, and

@@ -84,6 +84,8 @@ struct tpcf_handle_s {
     bool unit_w = true;
     bool self_lo = false;  // tpcf_run_catalogs with multipoles of L <= lmax only (no per-m export)
     bool self_cut = false;  // the summed self moments stop at order lmax (set by such a run)
+    int couple = -1;        // this pass's contraction may skip blocks with |l1 - l2| > couple (-1: none)
+    int couple_cut = -1;    // the summed blocks stop at |l1 - l2| <= couple_cut (set by tpcf_run_catalogs)
     DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
         d_catid, d_flag, d_istart, d_icell, d_icat, d_scanw, d_catbad;
     std::vector<int32_t> cat_status;  // per catalogue of the last tpcf_run_catalogs
@@ -820,6 +822,7 @@ tpcf_status contract_chunk(tpcf_handle h, const Chunk& ch) {
     c.unit_weights = h->unit_w ? 1 : 0;
     c.pw = P<float>(h->d_pw);
     c.ks_max = h->contract_step;
+    c.lcouple = h->couple >= 0 ? h->couple : h->lmax;
     if (h->cfg.flags & TPCF_F_ISOTROPIC) {
         // only the l1 = l2 blocks are formed; the rest of the partials is zero
         HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long*>(P<double>(h->d_part) + (int64_t)ch.sub_begin * h->gsize),
@@ -1092,8 +1095,15 @@ tpcf_status run_groups(tpcf_handle h, int32_t ncat, const int64_t* h_n, const in
         // keeps no per-m sums: the harmonic pass may stop them at lmax.
         h->self_lo = self_lo;
         h->self_cut = h->self_lo;
+        // The multipoles use only the blocks with |l1 - l2| <= L: the
+        // contraction may skip the others.
+        int lc = 0;
+        for (int t = 0; t < n_mult; ++t) lc = std::max(lc, std::abs(h_l1l2L[3 * t] - h_l1l2L[3 * t + 1]));
+        h->couple = n_mult > 0 && lc < h->lmax ? lc : -1;
+        h->couple_cut = h->couple;
         st = pair_pass(h, true);
         h->self_lo = false;
+        h->couple = -1;
         if (st != TPCF_OK) return st;
         if ((st = reduce_group(h)) != TPCF_OK) return st;
         h->stage = 3;
@@ -1192,6 +1202,7 @@ tpcf_status tpcf_build_grid(tpcf_handle h, const double* d_pos, const double* d_
     h->stage = 0;
     h->pairs_valid = false;
     h->self_cut = false;
+    h->couple_cut = -1;
     tpcf_status st = build_grid_group(h, d_pos, d_w, {n}, {n_data});
     if (st != TPCF_OK) return st;
     h->stage = 1;
@@ -1206,8 +1217,10 @@ tpcf_status tpcf_alm_accumulate(tpcf_handle h) {
     if (st != TPCF_OK) return st;
     if ((st = plan_chunks(h)) != TPCF_OK) return st;
     const bool single = h->chunks.size() == 1;
-    // the step calls keep every self-moment order (h->self_lo is false here)
+    // the step calls keep every self-moment order and every block (h->self_lo
+    // is false and h->couple is -1 here)
     h->self_cut = h->self_lo;
+    h->couple_cut = h->couple;
     if ((st = pair_pass(h, !single)) != TPCF_OK) return st;
     h->alm_kept = single;
     h->contracted_in_pass = !single;
@@ -1252,7 +1265,7 @@ tpcf_status tpcf_contract(tpcf_handle h, double* d_nnn_out) {
         h->stage = 3;
     }
     if (d_nnn_out) {
-        if (h->self_cut)
+        if (h->self_cut || h->couple_cut >= 0 || h->ncat != 1)
             return fail(h, TPCF_ERR_STATE, "tpcf_run_catalogs keeps no per-m sums; use the step calls");
         NnnArgs a{};
         a.G = P<double>(h->d_G);
@@ -1276,10 +1289,19 @@ tpcf_status tpcf_multipoles(tpcf_handle h, int32_t n_mult, const int32_t* h_l1l2
     if (st != TPCF_OK) return st;
     if (!d_out) return fail(h, TPCF_ERR_ARG, "d_out is NULL");
     if (h->stage < 3) return fail(h, TPCF_ERR_STATE, "tpcf_contract must come first");
+    // d_out holds one catalogue's multipoles
+    if (h->ncat != 1)
+        return fail(h, TPCF_ERR_STATE, "the handle holds the sums of " + std::to_string(h->ncat) +
+                                           " catalogues; tpcf_run_catalogs returns their multipoles");
     if (h->self_cut)
         for (int t = 0; t < n_mult; ++t)
             if (h_l1l2L[3 * t + 2] > h->lmax)
                 return fail(h, TPCF_ERR_STATE, "the self moments of the last tpcf_run_catalogs stop at order lmax");
+    if (h->couple_cut >= 0)
+        for (int t = 0; t < n_mult; ++t)
+            if (std::abs(h_l1l2L[3 * t] - h_l1l2L[3 * t + 1]) > h->couple_cut)
+                return fail(h, TPCF_ERR_STATE, "the last tpcf_run_catalogs summed only the blocks with |l1 - l2| <= " +
+                                                   std::to_string(h->couple_cut));
     HIPCHK(hipSetDevice(h->device));
     return finalize_group(h, n_mult, h_l1l2L, d_out);
 }
@@ -1731,6 +1753,7 @@ tpcf_status tpcf_autotune_plan(tpcf_handle h, int32_t ncat, const int64_t* h_n, 
     h->timing = timing;
     h->stage = 0;  // the sample's grid and sums are not kept
     h->self_cut = false;
+    h->couple_cut = -1;
     h->pairs_valid = false;
     if (st == TPCF_OK && best.ms < 0.0) st = fail(h, TPCF_ERR_ALLOC, "no plan fits the workspace");
     if (st != TPCF_OK) {

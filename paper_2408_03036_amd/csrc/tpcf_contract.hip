@@ -655,9 +655,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     const int nl = lmax - m + 1;
     const int K = nb * nl;
     const int nt = (K + TS - 1) / TS;
-    const int ntiles = nt * (nt + 1) / 2;
     const int t0 = blockIdx.z * kBfWaves * kBfTPW;
-    if (t0 >= ntiles) return;
     const int parts = m == 0 ? 1 : 2;
     const int NV = n_values(lmax);
     const int voff = value_offset(lmax, m);
@@ -675,14 +673,35 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     uint16_t* lds = reinterpret_cast<uint16_t*>(smem);
     const float* A = reinterpret_cast<const float*>(a.A);
 
+    // Columns are l-major (column c holds l - m = c / nb of bin c % nb), so
+    // the l of a 32-column tile spans a few consecutive values. The tiles of
+    // the upper triangle whose columns couple some l1, l2 with |l1 - l2| <=
+    // lcouple are the needed ones; this wave takes the (t0 + wave + 8 q)-th
+    // of them in row-major order. (Along a row of tiles the smallest l
+    // distance only grows, so a row ends at its first tile past the limit.)
     int ti[kBfTPW], tj[kBfTPW];
     bool tv[kBfTPW];
 #pragma unroll
     for (int q = 0; q < kBfTPW; ++q) {
-        const int t = t0 + wave + kBfWaves * q;
-        tv[q] = t < ntiles;
-        tile_of(tv[q] ? t : 0, nt, ti[q], tj[q]);
+        ti[q] = tj[q] = 0;
+        tv[q] = false;
     }
+    int nneed = 0;
+    for (int r = 0; r < nt; ++r) {
+        const int lhi = (min(K, r * TS + TS) - 1) / nb;
+        for (int c2 = r; c2 < nt; ++c2) {
+            if (c2 * TS / nb - lhi > a.lcouple) break;
+#pragma unroll
+            for (int q = 0; q < kBfTPW; ++q)
+                if (nneed == t0 + wave + kBfWaves * q) {
+                    ti[q] = r;
+                    tj[q] = c2;
+                    tv[q] = true;
+                }
+            ++nneed;
+        }
+    }
+    if (t0 >= nneed) return;
     f32x16 acc32[kBfTPW];
     double accd[kBfTPW][16];
 #pragma unroll
@@ -707,7 +726,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
     for (int u = 0; u < IPT; ++u) {
         const int it = threadIdx.x + u * 64 * kBfWaves;
         const int c = it / groups, k8 = (it - c * groups) * 8;
-        const int b = c / nl, lp = c - b * nl;
+        const int lp = c / nb, b = c - lp * nb;
         istore[u] = it < nitems;
         iok[u] = it < nitems && c < K;
         ik8[u] = k8;
@@ -858,6 +877,10 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
             __syncthreads();
         }
     }
+    // Each unordered column pair is written once (in a diagonal tile, the
+    // entry with the smaller l-major column first), at the upper-triangle
+    // position of the bin-major order c = b (lmax - m + 1) + l - m that the
+    // reduction, finalize and export read.
     const int64_t sg = (int64_t)(a.sub_base + s);
 #pragma unroll
     for (int q = 0; q < kBfTPW; ++q) {
@@ -867,7 +890,10 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_contract_bf16(ContractArgs a,
         for (int r = 0; r < 16; ++r) {
             const int ii = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
             const int ci = ti[q] * TS + ii, cj = tj[q] * TS + j;
-            if (ci < K && cj < K) a.part64[sg * a.gsize + a.goff[m] + (int64_t)ci * K + cj] = accd[q][r];
+            if (ci < K && cj < K && (ti[q] < tj[q] || ci <= cj)) {
+                const int oi = (ci % nb) * nl + ci / nb, oj = (cj % nb) * nl + cj / nb;
+                a.part64[sg * a.gsize + a.goff[m] + (int64_t)min(oi, oj) * K + max(oi, oj)] = accd[q][r];
+            }
         }
     }
 }

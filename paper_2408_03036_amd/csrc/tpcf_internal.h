@@ -226,6 +226,7 @@ struct ContractArgs {
     int unit_weights;        // all weights 1: skip the weight multiply
     const float* pw;         // FP32 weights, sorted order (split-BF16 modes)
     int ks_max;              // split-BF16: longest step in primaries (0: the longest that fits)
+    int lcouple;             // split-BF16: blocks with |l1 - l2| > lcouple may be skipped (>= lmax: none)
 };
 hipError_t launch_contract(const ContractArgs& a, hipStream_t s);
 // Isotropic schedule: only the l1 = l2 blocks of every G_m (nb <= 32); the

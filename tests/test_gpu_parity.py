@@ -371,9 +371,11 @@ def test_crowded_cluster_exact_rebinning(torch, prec):
 @pytest.mark.parametrize("prec", [T.PREC_FP32, T.PREC_MIXED_BF16X3])
 def test_run_catalogs_self_orders(torch, prec, weighted):
     """A batched run whose multipoles all have L <= lmax stops the self
-    moments at order lmax (the others cancel from every such multipole). Its
-    result equals that of the step calls, which keep every order, bit for bit;
-    afterwards the per-m export and multipoles of L > lmax are refused."""
+    moments at order lmax (the others cancel from every such multipole), and
+    its contraction skips the blocks of |l1 - l2| above its multipoles'. Its
+    result equals that of the step calls, which keep every order and block,
+    bit for bit; afterwards the per-m export, multipoles of L > lmax and
+    multipoles needing the skipped blocks are refused."""
     box, edges, lmax, n = 150.0, np.linspace(10.0, 40.0, 4), 4, 3000
     cats = [C.zeldovich(n, box, 3.0, 0.8, 151 + i, grid=32) for i in range(2)]
     ws = [np.random.default_rng(161 + i).uniform(0.5, 1.5, n) for i in range(2)] if weighted else [None, None]
@@ -389,6 +391,24 @@ def test_run_catalogs_self_orders(torch, prec, weighted):
     with pytest.raises(T.TpcfError) as e:
         h.multipoles([(4, 4, 6)])
     assert e.value.status == T.TPCF_ERR_STATE
+    # the handle holds two catalogues' sums: the one-catalogue multipole call
+    # is refused (its output has room for one)
+    with pytest.raises(T.TpcfError) as e:
+        h.multipoles(mults[:3])
+    assert e.value.status == T.TPCF_ERR_STATE
+    # A one-catalogue run: its contraction summed only the blocks with
+    # |l1 - l2| <= 2 (the largest of its multipoles). A triple needing
+    # |l1 - l2| = 4 is refused; one within the run's blocks is given, equal to
+    # the run's own result.
+    one = h.run_catalogs([n], [n], gpu(torch, cats[0]), gpu(torch, ws[0]) if weighted else None, mults)
+    h.sync()
+    assert np.array_equal(one.cpu().numpy()[0], batched[0])
+    with pytest.raises(T.TpcfError) as e:
+        h.multipoles([(0, 4, 4)])
+    assert e.value.status == T.TPCF_ERR_STATE
+    again = h.multipoles(mults[:3]).cpu().numpy()
+    h.sync()
+    assert np.array_equal(again, batched[0][:3])
     h.close()
     for i in range(2):
         h = T.Handle(box, edges, lmax, precision=prec)
