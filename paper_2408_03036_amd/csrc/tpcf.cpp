@@ -86,7 +86,7 @@ struct tpcf_handle_s {
     bool self_cut = false;  // the summed self moments stop at order lmax (set by such a run)
     int couple = -1;        // this pass's contraction may skip blocks with |l1 - l2| > couple (-1: none)
     int couple_cut = -1;    // the summed blocks stop at |l1 - l2| <= couple_cut (set by tpcf_run_catalogs)
-    DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
+    DevBuf d_pt_off, d_cellid, d_count, d_start, d_cursor, d_tmp, d_tmpz, d_orig, d_pf, d_pw, d_pa, d_pd, d_perm,
         d_catid, d_flag, d_istart, d_icell, d_icat, d_scanw, d_catbad;
     std::vector<int32_t> cat_status;  // per catalogue of the last tpcf_run_catalogs
     std::vector<int> item_cat;       // [ncat+1] first work item of each catalogue
@@ -545,6 +545,7 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     if ((st = ensure(h, h->d_scanw, sizeof(int) * grid_scan_work_ints(M))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_cursor, sizeof(int) * (M + 1))) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_tmp, sizeof(int) * N)) != TPCF_OK) return st;
+    if ((st = ensure(h, h->d_tmpz, sizeof(double) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_orig, sizeof(int) * N)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_pf, sizeof(float4) * N)) != TPCF_OK) return st;
     // 16 floats of padding: the contractions stage 8- and 16-wide windows
@@ -564,9 +565,9 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     HIPCHK(launch_grid_assign(d_pos, d_w, N, P<int64_t>(h->d_pt_off), h->ncat, h->g, P<int>(h->d_cellid),
                               P<int>(h->d_count), P<int>(h->d_flag), P<int>(h->d_catbad), h->stream));
     HIPCHK(launch_grid_scan(P<int>(h->d_count), M, P<int>(h->d_start), P<int>(h->d_scanw), h->stream));
-    HIPCHK(launch_grid_scatter(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_cursor),
-                               P<int>(h->d_tmp), h->stream));
-    HIPCHK(launch_grid_order(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_tmp),
+    HIPCHK(launch_grid_scatter(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_cursor), d_pos, h->g.box,
+                               P<int>(h->d_tmp), P<double>(h->d_tmpz), h->stream));
+    HIPCHK(launch_grid_order(P<int>(h->d_cellid), N, P<int>(h->d_start), P<int>(h->d_tmp), P<double>(h->d_tmpz),
                              P<int>(h->d_orig), h->stream));
     HIPCHK(launch_grid_fill(d_pos, d_w, N, P<int>(h->d_orig), P<int>(h->d_cellid), h->g, P<float4>(h->d_pf),
                             P<float>(h->d_pw), P<float4>(h->d_pa), P<double4>(h->d_pd), P<int>(h->d_perm), P<int>(h->d_catid),
@@ -738,6 +739,9 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     b.nfix_total = P<int>(h->d_flag) + 3;
     b.vol = P<double>(h->d_vol);
     b.inv_vst = (float)h->inv_vst;
+    // the reach of the per-item candidate cut: the outer edge with a margin
+    // of 1e-4 (relative), far above the FP32 rounding of the coordinates
+    b.reach2 = (float)(h->edges[h->nb] * h->edges[h->nb] * (1.0 + 2e-4));
     b.npmax = 2 * (int)h->runs.size();
     b.uniform = h->uniform;
     b.e0f = (float)h->edges[0];
@@ -1044,7 +1048,7 @@ tpcf_status run_groups(tpcf_handle h, int32_t ncat, const int64_t* h_n, const in
                        const double* d_pos, const double* d_w, bool self_lo, int32_t n_mult,
                        const int32_t* h_l1l2L, double* d_out, int32_t* status) {
     tpcf_status st;
-    const int64_t per_point = 96;
+    const int64_t per_point = 104;  // grid arrays per point (bytes)
     const int64_t max_pts = std::max<int64_t>(1, std::min<int64_t>((h->limit / 4) / per_point, (1LL << 31) - 1));
     int c0 = 0;
     int64_t pos_off = 0;
@@ -1176,7 +1180,7 @@ void tpcf_destroy(tpcf_handle h) {
     }
     DevBuf* all[] = {&h->d_e2, &h->d_e2f, &h->d_guard, &h->d_runs, &h->d_shift_f, &h->d_goff,
                      &h->d_vol, &h->d_scale, &h->d_sign_scale, &h->d_gaunt, &h->d_pt_off, &h->d_cellid,
-                     &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_orig, &h->d_pf, &h->d_pw,
+                     &h->d_count, &h->d_start, &h->d_cursor, &h->d_tmp, &h->d_tmpz, &h->d_orig, &h->d_pf, &h->d_pw,
                      &h->d_pa, &h->d_istart, &h->d_icell, &h->d_icat, &h->d_scanw, &h->d_catbad, &h->d_pd, &h->d_perm, &h->d_catid, &h->d_flag, &h->d_list, &h->d_fix, &h->d_lcursor, &h->d_boff,
                      &h->d_cnt, &h->d_A, &h->d_subs, &h->d_catsub, &h->d_part, &h->d_pself, &h->d_G,
                      &h->d_S, &h->d_nd, &h->d_mult, &h->d_coefG, &h->d_coefS, &h->d_lflag,

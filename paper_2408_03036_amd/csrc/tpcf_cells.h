@@ -65,18 +65,33 @@ __device__ inline double wrap_shift(int bits, int axis, double L) {
     return (double)(((bits >> (2 * axis)) & 3) - 1) * L;
 }
 
+// Bounding box of a work item's primaries in the home cell's frame, and the
+// squared reach beyond which no candidate can pair with any of them.
+struct ItemBox {
+    float xlo, xhi, ylo, yhi, zlo, zhi;
+    float r2;
+};
+
 // Builds the flattened candidate ranges of the primary in cell (cx,cy,cz).
 // Every stencil run (fixed ox, oy; oz in [oz_lo, oz_hi]) becomes at most two
 // pieces of consecutive cells: the part that wraps through the z boundary and
 // the part that does not.
 // A is any argument block with the grid (g), the stencil runs (runs, nruns)
 // and the per-cell point ranges (cell_start).
-template <class A>
-__device__ void build_pieces(Pieces& W, const A& a, int cat, int cx, int cy, int cz) {
+// CUT: the points of a cell are in increasing z (the grid's order), so along a
+// piece the candidates' z in the home frame, computed as the staging does,
+// never decreases. Each piece is cut to the candidates whose z lies within
+// the reach of the item's box over the xy gap to the piece's column (two
+// binary searches over the piece); a column beyond the reach is dropped. The
+// cut keeps every candidate within sqrt(box.r2) of a point of the box. The
+// uncut candidate count (the stencil's, for density estimates) goes to n[1].
+template <bool CUT = false, class A>
+__device__ void build_pieces(Pieces& W, const A& a, int cat, int cx, int cy, int cz,
+                             const ItemBox& box = ItemBox{}) {
     const int lane = lane_id();
     const int nc = a.g.nc, k = a.g.k, K2 = 2 * k + 1;
     const int base = cat * a.g.ncell;
-    int total_pieces = 0;
+    int total_pieces = 0, full = 0;
     for (int r0 = 0; r0 < a.nruns; r0 += 64) {
         const int r = r0 + lane;
         int s0 = 0, e0 = 0, s1 = 0, e1 = 0, c0 = 0, c1 = 0;
@@ -118,6 +133,47 @@ __device__ void build_pieces(Pieces& W, const A& a, int cat, int cx, int cy, int
                 zo1 = (float)(-cz);
                 c1 = cbk | ((wxy | (1 << 4)) << 16);
                 has_in = true;
+            }
+            full += (has_wrap ? e0 - s0 : 0) + (has_in ? e1 - s1 : 0);
+            if constexpr (CUT) {
+                const float hf = a.g.hf;
+                const float gx = fmaxf(0.f, fmaxf(sx - box.xhi, box.xlo - (sx + hf)));
+                const float gy = fmaxf(0.f, fmaxf(sy - box.yhi, box.ylo - (sy + hf)));
+                const float d2 = gx * gx + gy * gy;
+                if (d2 > box.r2) {
+                    has_wrap = has_in = false;
+                } else {
+                    const float hz = sqrtf(box.r2 - d2);
+                    const float zlo_c = box.zlo - hz, zhi_c = box.zhi + hz;
+                    // candidate j's z in the home frame, as stage_store forms it
+                    auto zh = [&](int j, float zo) {
+                        const float4 q = a.pf[j];
+                        return fmaf((float)(int)(q.w + zo), hf, q.z);
+                    };
+                    auto cut = [&](int& sb, int& se, float zo) {
+                        int lo = sb, hi = se;  // first candidate with z >= zlo_c
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (zh(mid, zo) < zlo_c) lo = mid + 1; else hi = mid;
+                        }
+                        const int b = lo;
+                        hi = se;  // first candidate past it with z > zhi_c
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (zh(mid, zo) <= zhi_c) lo = mid + 1; else hi = mid;
+                        }
+                        sb = b;
+                        se = lo;
+                    };
+                    if (has_wrap) {
+                        cut(s0, e0, zo0);
+                        has_wrap = e0 > s0;
+                    }
+                    if (has_in) {
+                        cut(s1, e1, zo1);
+                        has_in = e1 > s1;
+                    }
+                }
             }
         }
         const int np = (int)has_wrap + (int)has_in;
@@ -161,9 +217,11 @@ __device__ void build_pieces(Pieces& W, const A& a, int cat, int cx, int cy, int
         carry += __shfl(incl, 63, 64);
         wave_sync();
     }
+    for (int off = 32; off > 0; off >>= 1) full += __shfl_xor(full, off, 64);
     if (lane == 0) {
         W.pref[total_pieces] = carry;
-        *W.n = total_pieces;
+        W.n[0] = total_pieces;
+        W.n[1] = full;
     }
     wave_sync();
 }

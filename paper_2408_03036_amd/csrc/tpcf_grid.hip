@@ -3,8 +3,8 @@
 // the pair pass reads neighbour cells with coalesced loads).
 //
 // Steps: assign (wrap, cell id, histogram) -> scan (cell starts) ->
-// scatter (atomic slots) -> order (stable rank by input index inside a cell,
-// so the layout is deterministic) -> fill (sorted SoA copies).
+// scatter (atomic slots) -> order (rank by z, then input index, inside a
+// cell, so the layout is deterministic) -> fill (sorted SoA copies).
 #include "tpcf_internal.h"
 
 namespace tpcf {
@@ -137,26 +137,39 @@ __global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ coun
 
 __global__ void k_grid_scatter(const int* __restrict__ cellid, int64_t n,
                                const int* __restrict__ start, int* __restrict__ cursor,
-                               int* __restrict__ tmp_idx) {
+                               const double* __restrict__ pos, double box,
+                               int* __restrict__ tmp_idx, double* __restrict__ tmp_key) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = cellid[i];
     int slot = atomicAdd(&cursor[c], 1);
+    // the order key: the wrapped z the fill stores (0 for a non-finite point)
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const bool fin = isfinite(x) && isfinite(y) && isfinite(z);
     tmp_idx[start[c] + slot] = (int)i;
+    tmp_key[start[c] + slot] = wrap_coord(fin ? z : 0.0, box);
 }
 
-// Stable placement: a point's rank in its cell is the number of points of the
-// same cell with a smaller input index.
+// Placement inside a cell by z, ties by input index: a point's rank is the
+// number of points of its cell that come before it in that order. Along
+// every run of cells consecutive in z the points are then in increasing z,
+// which lets the pair pass cut a run to the z range a work item can reach.
+// The layout is deterministic.
 __global__ void k_grid_order(const int* __restrict__ cellid, int64_t n,
                              const int* __restrict__ start, const int* __restrict__ tmp_idx,
-                             int* __restrict__ orig) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c = cellid[i];
-    int a = start[c], b = start[c + 1];
+                             const double* __restrict__ tmp_key, int* __restrict__ orig) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = tmp_idx[s];
+    const double zi = tmp_key[s];
+    const int c = cellid[i];
+    const int a = start[c], b = start[c + 1];
     int rank = 0;
-    for (int s = a; s < b; ++s) rank += tmp_idx[s] < (int)i;
-    orig[a + rank] = (int)i;
+    for (int t = a; t < b; ++t) {
+        const double zt = tmp_key[t];
+        rank += zt < zi || (zt == zi && tmp_idx[t] < i);
+    }
+    orig[a + rank] = i;
 }
 
 __global__ void k_grid_fill(const double* __restrict__ pos, const double* __restrict__ w,
@@ -268,18 +281,18 @@ hipError_t launch_grid_scan(const int* count, int64_t m, int* start, int* work, 
 int64_t grid_scan_work_ints(int64_t m) { return 2 * ((m + kScanBlock - 1) / kScanBlock) + 1; }
 
 hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, int* cursor,
-                               int* tmp_idx, hipStream_t s) {
+                               const double* pos, double box, int* tmp_idx, double* tmp_key, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grid_scatter, dim3(nblk(n, 256)), dim3(256), 0, s, cellid, n, start,
-                       cursor, tmp_idx);
+                       cursor, pos, box, tmp_idx, tmp_key);
     return hipGetLastError();
 }
 
 hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, const int* tmp_idx,
-                             int* orig, hipStream_t s) {
+                             const double* tmp_key, int* orig, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_grid_order, dim3(nblk(n, 256)), dim3(256), 0, s, cellid, n, start,
-                       tmp_idx, orig);
+                       tmp_idx, tmp_key, orig);
     return hipGetLastError();
 }
 

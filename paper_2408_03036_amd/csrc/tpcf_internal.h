@@ -57,9 +57,9 @@ hipError_t launch_grid_assign(const double* pos, const double* w, int64_t n, con
 hipError_t launch_grid_scan(const int* count, int64_t m, int* start, int* work, hipStream_t s);
 int64_t grid_scan_work_ints(int64_t m);
 hipError_t launch_grid_scatter(const int* cellid, int64_t n, const int* start, int* cursor,
-                               int* tmp_idx, hipStream_t s);
+                               const double* pos, double box, int* tmp_idx, double* tmp_key, hipStream_t s);
 hipError_t launch_grid_order(const int* cellid, int64_t n, const int* start, const int* tmp_idx,
-                             int* orig, hipStream_t s);
+                             const double* tmp_key, int* orig, hipStream_t s);
 hipError_t launch_grid_fill(const double* pos, const double* w, int64_t n, const int* orig,
                             const int* cellid, Grid g, float4* pf, float* pw, float4* pa, double4* pd,
                             int* perm, int* catid, hipStream_t s);
@@ -100,6 +100,7 @@ struct BinArgs {
     int* nfix_total;         // [1] the fix-up launches add the lengths they processed
     const double* vol;       // [nb] shell volumes
     float inv_vst;           // 1 / stencil volume (the box in one-cell mode)
+    float reach2;            // squared reach of a work item's candidate cut (outer edge, with a margin)
     int npmax;               // capacity of the piece table (>= 2 nruns)
     int uniform;             // bins equally spaced in r: bin = floor((r - e0) / dr)
     float e0f, inv_dr;       // FP32 first edge and 1 / bin width (uniform bins)

@@ -167,7 +167,8 @@ struct ItemCtx {
     const BinTables* T;
     uint32_t* cnt;          // this wavefront's [kGM][kMaxBins] counters / write cursors
     const uint32_t* capoff; // bin regions of a primary's allocation (predicted capacities)
-    int np, total;
+    int np, total;          // pieces and candidates after the cut to the item
+    int total_full;         // candidates of the whole stencil (density estimate)
     int64_t cs, cstart;     // first primary of this wavefront's group, catalogue start
     uint32_t cst, mask;
     int cshift, cx, cy, cz, wave, lane, ng;
@@ -424,10 +425,42 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
     c.cst = (uint32_t)c.cstart;
     c.cshift = 32 - a.g.code_bits;
     c.mask = a.g.idx_mask;
-    if (c.wave == 0) build_pieces(S, a, cat, SINGLE ? 0 : c.cx, SINGLE ? 0 : c.cy, SINGLE ? 0 : c.cz);
+    if (c.wave == 0) {
+        if constexpr (SINGLE) {
+            build_pieces(S, a, cat, 0, 0, 0);
+        } else {
+            // The item's primaries bound the box the candidates are cut to:
+            // all of them, also where a chunk boundary splits the item, so
+            // that the cut, and with it the tiles and the order in which each
+            // list receives its hits, is the same in every chunking and batch.
+            const int64_t np_item = last - first;  // at most kItemPrims
+            float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (c.lane < np_item) P = a.pf[first + c.lane];
+            ItemBox box;
+            box.xlo = box.xhi = __shfl(P.x, 0, 64);
+            box.ylo = box.yhi = __shfl(P.y, 0, 64);
+            box.zlo = box.zhi = __shfl(P.z, 0, 64);
+            if (c.lane < np_item) {
+                box.xlo = P.x; box.xhi = P.x;
+                box.ylo = P.y; box.yhi = P.y;
+                box.zlo = P.z; box.zhi = P.z;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                box.xlo = fminf(box.xlo, __shfl_xor(box.xlo, o, 64));
+                box.xhi = fmaxf(box.xhi, __shfl_xor(box.xhi, o, 64));
+                box.ylo = fminf(box.ylo, __shfl_xor(box.ylo, o, 64));
+                box.yhi = fmaxf(box.yhi, __shfl_xor(box.yhi, o, 64));
+                box.zlo = fminf(box.zlo, __shfl_xor(box.zlo, o, 64));
+                box.zhi = fmaxf(box.zhi, __shfl_xor(box.zhi, o, 64));
+            }
+            box.r2 = a.reach2;
+            build_pieces<true>(S, a, cat, c.cx, c.cy, c.cz, box);
+        }
+    }
     __syncthreads();
-    c.np = *S.n;
+    c.np = S.n[0];
     c.total = S.pref[c.np];
+    c.total_full = S.n[1];
     const int lane = c.lane;
 
     // this wavefront's primaries: cs + wave + kNW g, g < ng
@@ -462,7 +495,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
         if (c.wave == 0) {
             int cap = 0;
             if (lane < a.nb) {
-                const float pred = (float)c.total * (float)a.vol[lane] * a.inv_vst;
+                const float pred = (float)c.total_full * (float)a.vol[lane] * a.inv_vst;
                 cap = (int)ceilf(1.15f * pred + 4.0f * sqrtf(pred) + 8.0f);
             }
             int incl = cap;
