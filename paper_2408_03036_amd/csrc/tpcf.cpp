@@ -1401,6 +1401,7 @@ tpcf_status tpcf_xi_count(tpcf_handle h, int32_t nmu, int64_t* d_counts) {
     a.inv_dr = h->inv_dr;
     a.delta = h->delta;
     a.inv_boxf = (float)(1.0 / h->cfg.box);
+    a.reach2 = (float)(h->edges[h->nb] * h->edges[h->nb] * (1.0 + 2e-4));
     a.nmu = nmu;
     a.hmu = nmu / 2.0;
     a.hmu_f = (float)a.hmu;

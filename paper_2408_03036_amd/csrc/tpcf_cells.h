@@ -72,6 +72,24 @@ struct ItemBox {
     float r2;
 };
 
+// Box of the primaries [first, last) (at most 64 points of one cell, in the
+// sorted order) in the home cell's frame, formed by one wavefront.
+__device__ inline ItemBox item_box(const float4* pf, int64_t first, int64_t last, float r2) {
+    const int lane = lane_id();
+    const bool in = lane < last - first;
+    const float4 P = pf[in ? first + lane : first];
+    ItemBox b{P.x, P.x, P.y, P.y, P.z, P.z, r2};
+    for (int o = 32; o > 0; o >>= 1) {
+        b.xlo = fminf(b.xlo, __shfl_xor(b.xlo, o, 64));
+        b.xhi = fmaxf(b.xhi, __shfl_xor(b.xhi, o, 64));
+        b.ylo = fminf(b.ylo, __shfl_xor(b.ylo, o, 64));
+        b.yhi = fmaxf(b.yhi, __shfl_xor(b.yhi, o, 64));
+        b.zlo = fminf(b.zlo, __shfl_xor(b.zlo, o, 64));
+        b.zhi = fmaxf(b.zhi, __shfl_xor(b.zhi, o, 64));
+    }
+    return b;
+}
+
 // Builds the flattened candidate ranges of the primary in cell (cx,cy,cz).
 // Every stencil run (fixed ox, oy; oz in [oz_lo, oz_hi]) becomes at most two
 // pieces of consecutive cells: the part that wraps through the z boundary and

@@ -168,6 +168,7 @@ struct XiArgs {
     int uniform;             // bins equally spaced in r
     float e0f, inv_dr, delta;// uniform bins: first edge, 1 / width, guard band in bin units
     float inv_boxf;          // 1 / L (single-cell mode)
+    float reach2;            // squared reach of a work item's candidate cut (outer edge, with a margin)
     int nmu;                 // mu bins over [-1, 1]
     float hmu_f;             // nmu / 2
     double hmu;

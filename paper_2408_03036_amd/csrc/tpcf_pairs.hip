@@ -430,30 +430,11 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             build_pieces(S, a, cat, 0, 0, 0);
         } else {
             // The item's primaries bound the box the candidates are cut to:
-            // all of them, also where a chunk boundary splits the item, so
-            // that the cut, and with it the tiles and the order in which each
-            // list receives its hits, is the same in every chunking and batch.
-            const int64_t np_item = last - first;  // at most kItemPrims
-            float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c.lane < np_item) P = a.pf[first + c.lane];
-            ItemBox box;
-            box.xlo = box.xhi = __shfl(P.x, 0, 64);
-            box.ylo = box.yhi = __shfl(P.y, 0, 64);
-            box.zlo = box.zhi = __shfl(P.z, 0, 64);
-            if (c.lane < np_item) {
-                box.xlo = P.x; box.xhi = P.x;
-                box.ylo = P.y; box.yhi = P.y;
-                box.zlo = P.z; box.zhi = P.z;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                box.xlo = fminf(box.xlo, __shfl_xor(box.xlo, o, 64));
-                box.xhi = fmaxf(box.xhi, __shfl_xor(box.xhi, o, 64));
-                box.ylo = fminf(box.ylo, __shfl_xor(box.ylo, o, 64));
-                box.yhi = fmaxf(box.yhi, __shfl_xor(box.yhi, o, 64));
-                box.zlo = fminf(box.zlo, __shfl_xor(box.zlo, o, 64));
-                box.zhi = fmaxf(box.zhi, __shfl_xor(box.zhi, o, 64));
-            }
-            box.r2 = a.reach2;
+            // all of them (at most kItemPrims), also where a chunk boundary
+            // splits the item, so that the cut, and with it the tiles and the
+            // order in which each list receives its hits, is the same in every
+            // chunking and batch.
+            const ItemBox box = item_box(a.pf, first, last, a.reach2);
             build_pieces<true>(S, a, cat, c.cx, c.cy, c.cz, box);
         }
     }

@@ -212,7 +212,12 @@ __global__ void __launch_bounds__(64 * kXW) k_xi_count(XiArgs a) {
         const int64_t first = (int64_t)a.cell_start[gc] + (int64_t)(item - a.item_start[gc]) * kItemPrims;
         const int64_t last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
         const int cz = gc % a.g.nc, cy = (gc / a.g.nc) % a.g.nc, cx = gc / (a.g.nc * a.g.nc);
-        if (wave == 0) build_pieces(S, a, 0, SINGLE ? 0 : cx, SINGLE ? 0 : cy, SINGLE ? 0 : cz);
+        if (wave == 0) {
+            // candidates cut to the reach of the item's primaries, as in the
+            // 3PCF binning (a pair within the outer edge keeps its candidate)
+            if constexpr (SINGLE) build_pieces(S, a, 0, 0, 0, 0);
+            else build_pieces<true>(S, a, 0, cx, cy, cz, item_box(a.pf, first, last, a.reach2));
+        }
         __syncthreads();
         const int total = S.pref[*S.n];
         const int rem = (int)(last - first);
