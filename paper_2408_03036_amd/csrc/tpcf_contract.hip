@@ -585,11 +585,13 @@ __global__ void __launch_bounds__(64 * kIsoWaves) k_contract_iso(ContractArgs a)
 }
 
 // ---------------------------------------------------------------- split-BF16 contraction
-// Eight wavefronts per workgroup, up to two 32x32 output tiles each. Per step
-// (KS primaries of one part), every thread stages 8 consecutive primaries of
-// one column: two vector loads, packed round-to-nearest BF16 conversion of the
-// pieces, one 16-byte LDS store per plane. Two LDS buffers: the loads of the
-// next step are in flight while the MFMAs of the current one run.
+// One workgroup per (subchunk, m): eight wavefronts, up to two 32x32 output
+// tiles each. Per step (KS primaries of one part, KS chosen per m), every
+// thread stages 8 consecutive primaries of one column: two vector loads,
+// packed round-to-nearest BF16 conversion of the pieces, one 16-byte LDS
+// store per plane. Two LDS buffers: the loads of the next step are in flight
+// while the MFMAs of the current one run. Columns are l-major, and a batched
+// run forms only the tiles its multipoles couple (lcouple).
 constexpr int kBfWaves = 8;
 constexpr int kBfTPW = 2;
 // staged 8-element groups per thread and step: four without weights, two with
@@ -602,9 +604,8 @@ struct BfSteps { int ks[kMaxLmax + 1]; };
 // Step length of one m: the longest power of two from cap down to 16 whose
 // staging fits the threads' registers (ncol * KS / 8 items of 8 primaries,
 // ipt per thread) and whose nbuf LDS buffers fit in lds bytes; 0 if none.
-// The narrow high-m operands thus take long steps: a workgroup's time goes
-// with its number of steps (each waits for its loads and a barrier), not
-// with its bytes.
+// The narrow high-m operands thus take long steps, and their workgroups
+// fewer of them: every step waits for its loads and a barrier.
 inline int bf_step(int ncol, int nplanes, int ipt, int nbuf, int cap, size_t lds) {
     for (int ks = cap; ks >= 16; ks /= 2) {
         if ((int64_t)ncol * (ks / 8) > (int64_t)64 * kBfWaves * ipt) continue;
