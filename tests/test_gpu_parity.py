@@ -316,6 +316,31 @@ def test_batched_equals_single_bitwise(torch, prec):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [T.PREC_MIXED_BF16X3, T.PREC_MIXED_BF16X6])
+@pytest.mark.parametrize("Lmax", [0, 2, 4])
+def test_coupled_tiles_only_batched_equals_steps(torch, prec, Lmax):
+    """lmax 10 with 10 bins: 110 columns at m = 0, four 32-column tiles a
+    side. A batched run whose multipoles have L <= Lmax forms only the tiles
+    that couple some |l1 - l2| <= Lmax (3 of the 10 of m = 0 skipped at Lmax
+    2); its multipoles equal those of the step calls, which form every tile,
+    bit for bit, and the oracle's within the tolerance."""
+    box, edges, lmax = 220.0, np.linspace(8.0, 48.0, 11), 10
+    pos = C.zeldovich(2500, box, 3.0, 0.8, 331 + Lmax, grid=32)
+    mults = O.all_multipoles(lmax, Lmax)
+    n = pos.shape[0]
+    h = T.Handle(box, edges, lmax, precision=prec)
+    batched = h.run_catalogs([n], [n], gpu(torch, pos), None, mults).cpu().numpy()[0]
+    h.sync()
+    h.close()
+    steps, npairs, _, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec)
+    assert np.array_equal(batched, steps)
+    ref, _, res = O.run(pos, box, edges, lmax, mults)
+    assert npairs == res.npairs
+    err = rel_err(batched, ref)
+    say(f"  coupled tiles {PNAME[prec]} Lmax {Lmax}: {len(mults)} multipoles, rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [T.PREC_FP64, T.PREC_FP32])
 def test_list_room_exhausted_pass_redone(torch, prec):
     """Half of the points in one tight clump: their pairs exceed the list room
