@@ -233,7 +233,7 @@ def test_single_cell_box_and_bins_from_zero(torch, prec):
     assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("refine", [1, 2, 3])
+@pytest.mark.parametrize("refine", [1, 2, 3, 4])
 def test_lmax0_exact_counts_every_grid(torch, refine):
     """lmax = 0: integer triplet counts, exact on every precision path and
     every neighbour-grid refinement (pins the pair set and the binning)."""
@@ -247,7 +247,7 @@ def test_lmax0_exact_counts_every_grid(torch, refine):
         assert err < 1e-12, (PNAME[prec], err)
 
 
-@pytest.mark.parametrize("refine", [1, 2, 3])
+@pytest.mark.parametrize("refine", [1, 2, 3, 4])
 def test_lattice_ties_full_items(torch, refine):
     """Half-spaced lattice (8 points per unit volume) with edges at multiples
     of 0.5: most pairs lie exactly on an edge, so nearly every test goes to the
