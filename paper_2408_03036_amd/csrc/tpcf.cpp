@@ -610,25 +610,31 @@ tpcf_status plan_chunks(tpcf_handle h) {
     for (int c = 0; c < h->ncat; ++c) maxn = std::max(maxn, h->pt_off[c + 1] - h->pt_off[c]);
     const double hits = std::min((double)maxn, maxn / L3 * shell);
     // hit lists: 4-byte entries (FP64 path) or 12/16-byte records (FP32 paths);
-    // room for the predicted bin regions of a primary of the densest
-    // catalogue (the binning kernel's margin), plus the rare exact rebins (a
+    // room for the predicted bin regions of each primary at its catalogue's
+    // mean density (the binning kernel's margin), plus the rare exact rebins (a
     // pass that runs out of room runs again with twice the room, and the
     // handle keeps the factor for the list room of its later passes)
     const double lelem = list_elem_bytes(h);
-    double hits_room = 64.0;
-    for (int b = 0; b < h->nb; ++b) {
-        const double pred = std::min((double)maxn, maxn / L3 * h->vol[b]);
-        hits_room += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
-    }
-    const double list_per = lelem * hits_room;
+    // list room per primary of a catalogue of n points
+    auto room_of = [&](int64_t n) {
+        double r = 64.0;
+        for (int b = 0; b < h->nb; ++b) {
+            const double pred = std::min((double)n, n / L3 * h->vol[b]);
+            r += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
+        }
+        return r;
+    };
+    std::vector<double> room(h->ncat);
+    for (int c = 0; c < h->ncat; ++c) room[c] = room_of(h->pt_off[c + 1] - h->pt_off[c]);
     h->hits_per_list = hits / h->nb;
-    int64_t budget = h->limit / 2;
-    int64_t cap = std::max<int64_t>(h->kc, (int64_t)(budget / (per_prim + list_per)));
-    cap = std::min<int64_t>(cap, 1 << 21);
-    // list offsets are 32-bit: keep a chunk's predicted room within 3.2e9
-    // entries, so that the 256 list regions get 15 % of slack within 4e9
-    cap = std::min<int64_t>(cap, (int64_t)(3.2e9 / hits_room));
-    cap = std::max<int64_t>(h->kc, cap / h->kc * h->kc);
+    const double budget = (double)(h->limit / 2);
+    // A chunk takes whole subchunks while its primaries stay within 2^21,
+    // its operand and predicted list room within the budget, and its list
+    // room within 3.2e9 entries (list offsets are 32-bit: the 256 list
+    // regions then get 15 % of slack within 4e9). The room of a subchunk is
+    // that of its own catalogue's density, so that a batch of uneven
+    // catalogues is not budgeted at the densest one.
+    const int64_t cap = 1 << 21;
     h->chunk_cap = cap;
     h->sub_start.clear();
     h->cat_sub.assign(h->ncat + 1, 0);
@@ -640,15 +646,28 @@ tpcf_status plan_chunks(tpcf_handle h) {
     h->sub_start.push_back(N);
     h->chunks.clear();
     const int nsub = (int)h->sub_start.size() - 1;
-    int s = 0;
+    int s = 0, cat = 0;
+    double max_room = 0.0;
     while (s < nsub) {
         Chunk ch;
         ch.sub_begin = s;
         ch.p_begin = h->sub_start[s];
-        while (s < nsub && h->sub_start[s + 1] - ch.p_begin <= cap) ++s;
-        if (s == ch.sub_begin) ++s;
+        int64_t n_acc = 0;
+        double r_acc = 0.0, b_acc = 0.0;
+        while (s < nsub) {
+            while (h->cat_sub[cat + 1] <= s) ++cat;
+            const int64_t n_s = h->sub_start[s + 1] - h->sub_start[s];
+            const double r_s = (double)n_s * room[cat];
+            const double b_s = (double)n_s * per_prim + lelem * r_s;
+            if (s > ch.sub_begin && (n_acc + n_s > cap || r_acc + r_s > 3.2e9 || b_acc + b_s > budget)) break;
+            n_acc += n_s;
+            r_acc += r_s;
+            b_acc += b_s;
+            ++s;
+        }
         ch.sub_end = s;
         ch.p_end = h->sub_start[s];
+        max_room = std::max(max_room, r_acc);
         h->chunks.push_back(ch);
     }
     int64_t maxch = 0;
@@ -677,7 +696,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     // regions to their prediction on average, and the 256 regions differ
     // times the growth earlier passes of this handle needed (strong
     // clustering); the chunk sizes keep the prediction
-    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, 1.15 * (double)maxch * hits_room * h->list_grow));
+    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, 1.15 * max_room * h->list_grow));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
