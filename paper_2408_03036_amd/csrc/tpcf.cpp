@@ -620,7 +620,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
         double r = 64.0;
         for (int b = 0; b < h->nb; ++b) {
             const double pred = std::min((double)n, n / L3 * h->vol[b]);
-            r += 1.15 * pred + 4.0 * std::sqrt(pred) + 9.0;
+            r += 1.15 * pred + 4.0 * std::sqrt(pred) + 10.0;
         }
         return r;
     };
@@ -630,8 +630,8 @@ tpcf_status plan_chunks(tpcf_handle h) {
     const double budget = (double)(h->limit / 2);
     // A chunk takes whole subchunks while its primaries stay within 2^21,
     // its operand and predicted list room within the budget, and its list
-    // room within 3.2e9 entries (list offsets are 32-bit: the 256 list
-    // regions then get 15 % of slack within 4e9). The room of a subchunk is
+    // room within 6.4e9 entries (list offsets are 32-bit counts of entry
+    // pairs: the 256 list regions then get 15 % of slack within 8e9). The room of a subchunk is
     // that of its own catalogue's density, so that a batch of uneven
     // catalogues is not budgeted at the densest one.
     const int64_t cap = 1 << 21;
@@ -659,7 +659,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
             const int64_t n_s = h->sub_start[s + 1] - h->sub_start[s];
             const double r_s = (double)n_s * room[cat];
             const double b_s = (double)n_s * per_prim + lelem * r_s;
-            if (s > ch.sub_begin && (n_acc + n_s > cap || r_acc + r_s > 3.2e9 || b_acc + b_s > budget)) break;
+            if (s > ch.sub_begin && (n_acc + n_s > cap || r_acc + r_s > 6.4e9 || b_acc + b_s > budget)) break;
             n_acc += n_s;
             r_acc += r_s;
             b_acc += b_s;
@@ -696,7 +696,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     // regions to their prediction on average, and the 256 regions differ
     // times the growth earlier passes of this handle needed (strong
     // clustering); the chunk sizes keep the prediction
-    h->list_cap = (unsigned long long)std::min(4.0e9, std::max(1.0e6, 1.15 * max_room * h->list_grow));
+    h->list_cap = (unsigned long long)std::min(8.0e9, std::max(1.0e6, 1.15 * max_room * h->list_grow));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
@@ -749,7 +749,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     b.rec3 = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
     b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
     b.cursor = P<unsigned long long>(h->d_lcursor);
-    b.capacity = h->list_cap;
+    b.capacity = h->list_cap / 2;  // in entry pairs, the unit of the list offsets
     b.boff = P<uint32_t>(h->d_boff);
     b.cnt = P<uint32_t>(h->d_cnt);
     b.overflow = P<int>(h->d_flag) + 1;
@@ -979,7 +979,7 @@ tpcf_status pair_pass(tpcf_handle h, bool contract_now) {
         HIPCHK(hipStreamSynchronize(h->stream));
         h->nfix_total += flag[2];
         if (!flag[0]) return TPCF_OK;
-        const unsigned long long ncap = std::min<unsigned long long>(4000000000ull, h->list_cap * 2);
+        const unsigned long long ncap = std::min<unsigned long long>(8000000000ull, h->list_cap * 2);
         if (attempt == 5 || ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
         h->list_cap = ncap;
         h->list_grow = std::min(h->list_grow * 2.0, 64.0);  // kept for the next groups and calls

@@ -90,9 +90,9 @@ struct BinArgs {
     uint32_t* list;          // hit lists of the chunk (list entries), or
     float4* rec;             // hit records (dx, dy, dz, w_j) when not null (FP32 paths)
     int rec3;                // 12-byte records (dx, dy, dz): unit weights, read by the whole-m FP32 kernels
-    unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each
-    unsigned long long capacity;
-    uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists
+    unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each (in entry pairs)
+    unsigned long long capacity;  // room of `list` in entry pairs (two entries or records)
+    uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists, in entry pairs (every list starts at an even entry)
     uint32_t* cnt;           // [(p_end-p_begin)*nb] lengths
     int* overflow;           // [1] set when `list` is too small
     int2* fix;               // fix-up list: (cell, chunk-relative primary) whose predicted bin regions overflowed

@@ -205,13 +205,14 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
         // the lists are the same on every run
         const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
         if (SWEEP == 2 && pos >= c.capoff[b + 1]) return;
+        // base_g counts pairs of slots (list offsets in units of two)
+        const size_t at = 2 * (size_t)base_g + pos;
         if constexpr (REC == 3) {
-            *reinterpret_cast<float3*>(reinterpret_cast<float*>(a.rec) + 3 * (size_t)(base_g + pos)) =
-                make_float3(dx, dy, dz);
+            *reinterpret_cast<float3*>(reinterpret_cast<float*>(a.rec) + 3 * at) = make_float3(dx, dy, dz);
         } else if constexpr (REC == 4) {
-            a.rec[base_g + pos] = make_float4(dx, dy, dz, w);
+            a.rec[at] = make_float4(dx, dy, dz, w);
         } else {
-            a.list[base_g + pos] = entry;
+            a.list[at] = entry;
         }
     }
 }
@@ -346,31 +347,35 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
 // (offset, count) of every (p, b) is published.
 __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]) {
     const int lane = c.lane;
+    // each bin's room is its count rounded up to even: list offsets are
+    // published in units of two slots
     uint32_t tot[kGM], cl[kGM], ex[kGM];
     uint32_t sum = 0;
 #pragma unroll
     for (int g = 0; g < kGM; ++g) {
         tot[g] = cl[g] = ex[g] = 0;
         if (g >= c.ng) continue;
-        const int cv = lane < a.nb ? (int)c.cnt[g * kMaxBins + lane] : 0;
+        const int cn = lane < a.nb ? (int)c.cnt[g * kMaxBins + lane] : 0;
+        const int cv = (cn + 1) & ~1;
         int incl = cv;
         for (int o = 1; o < 64; o <<= 1) {
             const int v = __shfl_up(incl, o, 64);
             if (lane >= o) incl += v;
         }
         tot[g] = (uint32_t)__shfl(incl, 63, 64);
-        cl[g] = (uint32_t)cv;
+        cl[g] = (uint32_t)cn;
         ex[g] = (uint32_t)(incl - cv);
         if (lane < a.nb) c.cnt[g * kMaxBins + lane] = ex[g];
         sum += tot[g];
     }
     if (c.ng == 0) return;
     const int slot = c.slot;
+    // cursors, regions and the capacity count units of two slots
     const unsigned long long region = a.capacity / kSlots;
     unsigned long long b0 = 0;
-    if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)sum);
+    if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)(sum / 2));
     b0 = __shfl(b0, 0, 64);
-    const bool ok = b0 + sum <= region;
+    const bool ok = b0 + sum / 2 <= region;
     if (!ok && lane == 0) atomicOr(a.overflow, 1);
     uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
 #pragma unroll
@@ -379,10 +384,10 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
         const int64_t pl = c.cs + c.wave + kNW * g - a.p_begin;
         if (lane < a.nb) {
             a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
-            a.boff[pl * a.nb + lane] = ok ? run + ex[g] : 0u;
+            a.boff[pl * a.nb + lane] = ok ? run + ex[g] / 2 : 0u;
         }
         if (ok) base[g] = run;
-        run += tot[g];
+        run += tot[g] / 2;
     }
 }
 
@@ -477,7 +482,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             int cap = 0;
             if (lane < a.nb) {
                 const float pred = (float)c.total_full * (float)a.vol[lane] * a.inv_vst;
-                cap = (int)ceilf(1.15f * pred + 4.0f * sqrtf(pred) + 8.0f);
+                cap = ((int)ceilf(1.15f * pred + 4.0f * sqrtf(pred) + 8.0f) + 1) & ~1;  // even: offsets count pairs
             }
             int incl = cap;
             for (int o = 1; o < 64; o <<= 1) {
@@ -492,7 +497,8 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             c.cnt[i] = (i % kMaxBins) < a.nb ? T.capoff[i % kMaxBins] : 0u;
         bool ok = true;
         if (c.ng > 0) {
-            const unsigned long long sum = (unsigned long long)captot * (unsigned)c.ng;
+            // in units of two slots (every bin's capacity is even)
+            const unsigned long long sum = (unsigned long long)(captot / 2) * (unsigned)c.ng;
             const int slot = c.slot;
             const unsigned long long region = a.capacity / kSlots;
             unsigned long long b0 = 0;
@@ -503,7 +509,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             const uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
 #pragma unroll
             for (int g = 0; g < kGM; ++g)
-                if (ok && g < c.ng) base[g] = run + (uint32_t)g * captot;
+                if (ok && g < c.ng) base[g] = run + (uint32_t)g * (captot / 2);
         }
         wave_sync();
         bin_sweep<2, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
@@ -526,7 +532,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             if (lane < a.nb) {
                 const bool pub = ok && !over;
                 a.cnt[pl * a.nb + lane] = pub ? cv : 0u;
-                a.boff[pl * a.nb + lane] = pub ? base[g] + co : 0u;
+                a.boff[pl * a.nb + lane] = pub ? base[g] + co / 2 : 0u;
             }
         }
     }
@@ -857,7 +863,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // three waves).
         constexpr int K = AC::NA + AC::NS > 128 ? 8 : 4;
         // an empty list reads the first record of the buffer (not accumulated)
-        const size_t roff = n > 0 ? off : 0;
+        const size_t roff = n > 0 ? 2 * (size_t)off : 0;  // offsets count pairs of records
         const uint32_t last = n > 0 ? n - 1 : 0;
         // with UNIT the records are 12 bytes (dx, dy, dz)
         const float4* rec = a.rec + roff;
@@ -906,7 +912,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         const int64_t cstart = a.pt_off[a.catid[pself]];
         const double4 P64 = a.pd[pself];
         const uint32_t mask = a.g.idx_mask;
-        const uint32_t* lst = n > 0 ? a.list + off : a.list;
+        const uint32_t* lst = n > 0 ? a.list + 2 * (size_t)off : a.list;  // offsets count pairs of entries
         const uint32_t last = n > 0 ? n - 1 : 0;
         auto entry = [&](uint32_t r) { return lst[min(r, last)]; };
         auto gather = [&](uint32_t r, uint32_t e) { return a.pd[r < n ? cstart + (int64_t)(e & mask) : pself]; };
@@ -997,7 +1003,7 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
     // the same ping-pong of unconditional loads as the lane-per-list kernel,
     // over blocks of 64 consecutive records (n is uniform over the wavefront)
     constexpr int K = 2;
-    const size_t roff = n > 0 ? a.boff[pl * a.nb + b] : 0;
+    const size_t roff = n > 0 ? 2 * (size_t)a.boff[pl * a.nb + b] : 0;  // offsets count pairs of records
     const uint32_t last = n > 0 ? n - 1 : 0;
     // with UNIT the records are 12 bytes (dx, dy, dz)
     const float4* rec = a.rec + roff;
