@@ -693,8 +693,9 @@ def main():
 
     print(f"[bench] {args.precision}: {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
+    # 160 GiB of the 288 GB: chunks of 2^21 primaries with their hit lists
     h = T.Handle(box, edges, lmax, precision=prec_id, flags=flags, grid_refine=args.refine,
-                 workspace_limit=96 << 30)
+                 workspace_limit=160 << 30)
     plan = tune(h, sizes, pos, None, sizes, args)
     h.set_timing(True)
     rebinned0 = h.rebinned_count()  # the tuner's passes are not counted

@@ -631,7 +631,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     // A chunk takes whole subchunks while its primaries stay within 2^21,
     // its operand and predicted list room within the budget, and its list
     // room within 6.4e9 entries (list offsets are 32-bit counts of entry
-    // pairs: the 256 list regions then get 15 % of slack within 8e9). The room of a subchunk is
+    // pairs: the list regions then get 15 % of slack within 8e9). The room of a subchunk is
     // that of its own catalogue's density, so that a batch of uneven
     // catalogues is not budgeted at the densest one.
     const int64_t cap = 1 << 21;
@@ -750,6 +750,9 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
     b.cursor = P<unsigned long long>(h->d_lcursor);
     b.capacity = h->list_cap / 2;  // in entry pairs, the unit of the list offsets
+    // at least ~64 work items (of at most 16 primaries) per region, so that
+    // the regions, taken by the items in turn, fill evenly within the slack
+    b.nslots = (int)std::min<int64_t>(kSlots, std::max<int64_t>(1, (ch.p_end - ch.p_begin) / 1024));
     b.boff = P<uint32_t>(h->d_boff);
     b.cnt = P<uint32_t>(h->d_cnt);
     b.overflow = P<int>(h->d_flag) + 1;
@@ -769,7 +772,6 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     b.inv_boxf = (float)(1.0 / h->g.box);
     b.item_start = P<int>(h->d_istart);
     b.item_cell = P<int>(h->d_icell);
-    b.slot_stretch = (double)h->npts >= 12.0 * (double)h->ncat * h->g.ncell ? 1 : 0;
     {
         // work items of the catalogues holding the chunk's primaries
         int c0 = 0, c1 = 0;

@@ -30,7 +30,8 @@ struct BinTables {
     double e2[kMaxBins + 1];
     float e2f[kMaxBins + 1];
     float guard[kMaxBins + 1];
-    uint32_t capoff[kMaxBins + 1];  // list layout of a primary: bin b at [capoff[b], capoff[b+1])
+    uint32_t capoff[kMaxBins + 1];  // predicted regions of a primary: bin b has capoff[b+1] - capoff[b] slots
+    uint32_t ibase;                 // the work item's list allocation (entry pairs), or kNoBase
 };
 
 // Candidate table of a home cell in LDS. Pieces are runs of consecutive cells

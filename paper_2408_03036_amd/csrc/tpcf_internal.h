@@ -92,6 +92,7 @@ struct BinArgs {
     int rec3;                // 12-byte records (dx, dy, dz): unit weights, read by the whole-m FP32 kernels
     unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each (in entry pairs)
     unsigned long long capacity;  // room of `list` in entry pairs (two entries or records)
+    int nslots;              // regions the room is split into, one cursor each (<= kSlots)
     uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists, in entry pairs (every list starts at an even entry)
     uint32_t* cnt;           // [(p_end-p_begin)*nb] lengths
     int* overflow;           // [1] set when `list` is too small
@@ -109,7 +110,6 @@ struct BinArgs {
     const int* item_start;   // [ncat*ncell+1] first work item of each cell
     const int* item_cell;    // [items] cell of each work item
     int64_t item_lo, item_hi;// work items of the catalogues holding the chunk's primaries
-    int slot_stretch;        // cells of 12+ points on average: spread list regions (see k_pair_bin)
 };
 constexpr int kSlots = 256;  // list allocation cursors (each on its own 128-byte line)
 hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s);

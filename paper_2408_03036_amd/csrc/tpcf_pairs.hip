@@ -166,7 +166,7 @@ struct ItemCtx {
     uint32_t* tent;         // [2][kTile] their list entries
     const BinTables* T;
     uint32_t* cnt;          // this wavefront's [kGM][kMaxBins] counters / write cursors
-    const uint32_t* capoff; // bin regions of a primary's allocation (predicted capacities)
+    uint32_t* end;          // this wavefront's [kGM][kMaxBins] ends of the predicted regions
     int np, total;          // pieces and candidates after the cut to the item
     int total_full;         // candidates of the whole stencil (density estimate)
     int64_t cs, cstart;     // first primary of this wavefront's group, catalogue start
@@ -204,7 +204,7 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
         // the LDS unit serves the lanes of one atomic in a fixed order, so
         // the lists are the same on every run
         const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
-        if (SWEEP == 2 && pos >= c.capoff[b + 1]) return;
+        if (SWEEP == 2 && pos >= c.end[g * kMaxBins + b]) return;
         // base_g counts pairs of slots (list offsets in units of two)
         const size_t at = 2 * (size_t)base_g + pos;
         if constexpr (REC == 3) {
@@ -220,7 +220,7 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
 // One sweep over the item's candidates. SWEEP 0 counts the hits of every
 // (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
 // bin), the offsets having been prepared in cnt; SWEEP 2 does the same inside
-// the predicted bin regions capoff, and drops (but still counts) the hits
+// the predicted regions (their ends in end), and drops (but still counts) the hits
 // beyond a region's end. A hit is written as a list entry, or (REC 3 or 4) as
 // the record that the FP32 harmonic pass streams.
 //
@@ -371,7 +371,7 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
     if (c.ng == 0) return;
     const int slot = c.slot;
     // cursors, regions and the capacity count units of two slots
-    const unsigned long long region = a.capacity / kSlots;
+    const unsigned long long region = a.capacity / a.nslots;
     unsigned long long b0 = 0;
     if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)(sum / 2));
     b0 = __shfl(b0, 0, 64);
@@ -408,16 +408,8 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
 // thread of the workgroup calls it with the same item.
 template <bool SINGLE, bool UNIFORM, int REC, bool FIX>
 __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S, BinTables& T, int gc,
-                                         int64_t first, int64_t last) {
-    // The region follows the wavefront's first primary pl0 (chunk-relative),
-    // which spreads evenly when cells are small (items rarely full). With
-    // full items of 16 primaries (large cells) that would use only a quarter
-    // of the regions; there pl0 is stretched by a quarter, pl0 + 4 floor(pl0 / 16),
-    // which steps through all of them (by 20 per item).
-    {
-        const int64_t pl0 = max(first, a.p_begin) + c.wave - a.p_begin;
-        c.slot = (int)((a.slot_stretch ? pl0 + 4 * (pl0 >> 4) : pl0) % kSlots);
-    }
+                                         int64_t first, int64_t last, int slot) {
+    c.slot = slot;
     c.cs = max(first, a.p_begin);
     const int64_t ce = min(last, a.p_end);
     if (c.cs >= ce) return;
@@ -477,7 +469,14 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
         bin_sweep<1, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
         return;
     } else {
-        // predicted regions, the same for every primary of the item
+        // Predicted regions, the same for every primary of the item, and one
+        // allocation for the item's primaries of this chunk, laid out bin by
+        // bin: bin b holds the lists of capacity cap_b of primaries 0 .. n-1
+        // side by side. A harmonic wavefront reads one bin of consecutive
+        // primaries, so its lists lie in a few items' blocks rather than in
+        // as many places as it has lanes (the gathers of the FP64 pass were
+        // measured bound by the address translations of that spread).
+        const int nitem = (int)(ce - c.cs);
         if (c.wave == 0) {
             int cap = 0;
             if (lane < a.nb) {
@@ -490,27 +489,37 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
                 if (lane >= o) incl += v;
             }
             if (lane <= a.nb) T.capoff[lane] = (uint32_t)(incl - cap);
+            const uint32_t captot = (uint32_t)__shfl(incl, 63, 64);
+            if (lane == 0) {
+                // in units of two slots (every capacity is even)
+                const unsigned long long sum = (unsigned long long)(captot / 2) * (unsigned)nitem;
+                const unsigned long long region = a.capacity / a.nslots;
+                const int slot = c.slot;
+                const unsigned long long b0 = atomicAdd(a.cursor + slot * 16, sum);
+                const bool fits = b0 + sum <= region;
+                if (!fits) atomicOr(a.overflow, 1);
+                T.ibase = fits ? (uint32_t)(b0 + (unsigned long long)slot * region) : kNoBase;
+            }
         }
         __syncthreads();
-        const uint32_t captot = T.capoff[a.nb];
-        for (int i = lane; i < kGM * kMaxBins; i += 64)
-            c.cnt[i] = (i % kMaxBins) < a.nb ? T.capoff[i % kMaxBins] : 0u;
-        bool ok = true;
-        if (c.ng > 0) {
-            // in units of two slots (every bin's capacity is even)
-            const unsigned long long sum = (unsigned long long)(captot / 2) * (unsigned)c.ng;
-            const int slot = c.slot;
-            const unsigned long long region = a.capacity / kSlots;
-            unsigned long long b0 = 0;
-            if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, sum);
-            b0 = __shfl(b0, 0, 64);
-            ok = b0 + sum <= region;
-            if (!ok && lane == 0) atomicOr(a.overflow, 1);
-            const uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
-#pragma unroll
-            for (int g = 0; g < kGM; ++g)
-                if (ok && g < c.ng) base[g] = run + (uint32_t)g * (captot / 2);
+        const uint32_t ibase = T.ibase;
+        const bool ok = ibase != kNoBase;
+        // write cursor and region end of (primary wave + kNW g, bin b): the
+        // region [nitem capoff[b] + i cap_b, + cap_b) of the item's allocation
+        for (int i = lane; i < kGM * kMaxBins; i += 64) {
+            const int g = i / kMaxBins, b = i % kMaxBins;
+            uint32_t st = 0, cb = 0;
+            if (b < a.nb) {
+                const uint32_t co = T.capoff[b];
+                cb = T.capoff[b + 1] - co;
+                st = (uint32_t)nitem * co + (uint32_t)(c.wave + kNW * g) * cb;
+            }
+            c.cnt[i] = st;
+            c.end[i] = st + cb;
         }
+#pragma unroll
+        for (int g = 0; g < kGM; ++g)
+            if (g < c.ng) base[g] = ibase;
         wave_sync();
         bin_sweep<2, SINGLE, UNIFORM, REC>(a, c, px, py, pz, base);
         wave_sync();
@@ -518,11 +527,11 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
         for (int g = 0; g < kGM; ++g) {
             if (g >= c.ng) continue;
             const int64_t pl = c.cs + c.wave + kNW * g - a.p_begin;
-            uint32_t cv = 0, cap = 0, co = 0;
+            uint32_t cv = 0, cap = 0, st = 0;
             if (lane < a.nb) {
-                co = T.capoff[lane];
-                cap = T.capoff[lane + 1] - co;
-                cv = c.cnt[g * kMaxBins + lane] - co;
+                cap = T.capoff[lane + 1] - T.capoff[lane];
+                st = c.end[g * kMaxBins + lane] - cap;
+                cv = c.cnt[g * kMaxBins + lane] - st;
             }
             const bool over = __ballot(lane < a.nb && cv > cap) != 0;
             if (over && ok && lane == 0) {
@@ -532,7 +541,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             if (lane < a.nb) {
                 const bool pub = ok && !over;
                 a.cnt[pl * a.nb + lane] = pub ? cv : 0u;
-                a.boff[pl * a.nb + lane] = pub ? base[g] + co / 2 : 0u;
+                a.boff[pl * a.nb + lane] = pub ? ibase + st / 2 : 0u;
             }
         }
     }
@@ -560,11 +569,11 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
     c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     c.lane = lane_id();
     c.cnt = reinterpret_cast<uint32_t*>(smem + off) + c.wave * (kGM * kMaxBins);
+    c.end = reinterpret_cast<uint32_t*>(smem + off) + (kNW + c.wave) * (kGM * kMaxBins);
     c.T = &T;
     c.S = &S;
     c.tiles = tiles;
     c.tent = tent;
-    c.capoff = T.capoff;
 
     if constexpr (FIX) {
         // the fix-up list the binning launch left on the device, walked by a
@@ -574,7 +583,9 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
         for (int64_t item = blockIdx.x; item < nfix; item += gridDim.x) {
             const int2 f = a.fix[item];
             __syncthreads();  // the previous item's pieces and tiles are no longer read
-            bin_item<SINGLE, UNIFORM, REC, true>(a, c, S, T, f.x, a.p_begin + f.y, a.p_begin + f.y + 1);
+            // a fix-up item (one primary) allocates from the region of its primary
+            bin_item<SINGLE, UNIFORM, REC, true>(a, c, S, T, f.x, a.p_begin + f.y, a.p_begin + f.y + 1,
+                                                 f.y % a.nslots);
         }
     } else {
         const int64_t item = a.item_lo + xcd_block(blockIdx.x, (int64_t)gridDim.x);
@@ -582,7 +593,10 @@ __global__ void __launch_bounds__(64 * kNW) k_pair_bin(BinArgs a) {
         const int gc = a.item_cell[item];
         const int64_t first = (int64_t)a.cell_start[gc] + (item - a.item_start[gc]) * kItemPrims;
         const int64_t last = min(first + kItemPrims, (int64_t)a.cell_start[gc + 1]);
-        bin_item<SINGLE, UNIFORM, REC, false>(a, c, S, T, gc, first, last);
+        // consecutive items take the regions in turn: the items that hold
+        // the chunk's primaries are consecutive, so every region gets the
+        // same share of them (to within one)
+        bin_item<SINGLE, UNIFORM, REC, false>(a, c, S, T, gc, first, last, (int)((item - a.item_lo) % a.nslots));
     }
 }
 
@@ -1194,7 +1208,7 @@ hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {
 size_t pair_bin_lds_bytes(int npmax) {
     return (sizeof(BinTables) + 15) / 16 * 16 + (sizeof(float4) + sizeof(uint32_t)) * 2 * kTile +
            pieces_lds_bytes(npmax) +
-           sizeof(uint32_t) * kNW * kGM * kMaxBins;
+           sizeof(uint32_t) * 2 * kNW * kGM * kMaxBins;
 }
 
 }  // namespace tpcf
