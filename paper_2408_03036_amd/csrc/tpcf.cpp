@@ -588,12 +588,12 @@ tpcf_status build_grid_group(tpcf_handle h, const double* d_pos, const double* d
     return TPCF_OK;
 }
 
-// Bytes per hit in the neighbour lists.
-// Bytes per hit: 4-byte list entries (FP64 path), 16-byte records (FP32), or
-// 12-byte records with unit weights at lmax <= 10 (as the binning writes them).
+// Bytes per hit in the neighbour lists: 4-byte list entries (FP64 path),
+// 16-byte records (FP32), or 8-byte direction codes with unit weights at
+// lmax <= 10 (as the binning writes them).
 size_t list_elem_bytes(tpcf_handle h) {
     if (h->fp64) return sizeof(uint32_t);
-    return (h->unit_w && h->lmax <= 10) ? 3 * sizeof(float) : sizeof(float4);
+    return (h->unit_w && h->lmax <= 10) ? 2 * sizeof(float) : sizeof(float4);
 }
 
 // Splits every catalogue into subchunks of kc primaries and groups whole
@@ -745,8 +745,8 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     b.rec = h->fp64 ? nullptr : P<float4>(h->d_list);
     // unit weights with the whole m range in one FP32 lane (lmax <= 10):
     // the harmonic kernels that read the records (their UNIT forms) take
-    // no weight, so a record is (dx, dy, dz)
-    b.rec3 = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
+    // no weight, and only the direction: a record is its octahedral code
+    b.rec_oct = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
     b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
     b.cursor = P<unsigned long long>(h->d_lcursor);
     b.capacity = h->list_cap / 2;  // in entry pairs, the unit of the list offsets

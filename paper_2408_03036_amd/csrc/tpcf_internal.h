@@ -89,7 +89,7 @@ struct BinArgs {
     int64_t p_begin, p_end;  // primaries (sorted indices) of this chunk
     uint32_t* list;          // hit lists of the chunk (list entries), or
     float4* rec;             // hit records (dx, dy, dz, w_j) when not null (FP32 paths)
-    int rec3;                // 12-byte records (dx, dy, dz): unit weights, read by the whole-m FP32 kernels
+    int rec_oct;             // 8-byte records, the octahedral code of the direction: unit weights, read by the whole-m FP32 kernels
     unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each (in entry pairs)
     unsigned long long capacity;  // room of `list` in entry pairs (two entries or records)
     int nslots;              // regions the room is split into, one cursor each (<= kSlots)

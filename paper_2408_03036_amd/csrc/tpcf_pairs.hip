@@ -98,6 +98,36 @@ constexpr NearMask near_primary_bits() {
 }
 constexpr NearMask kNearPrimary = near_primary_bits();
 constexpr uint32_t kNoBase = 0xffffffffu;
+
+// Octahedral code of a direction, the 8-byte record of a hit with unit
+// weights: the point d / (|dx| + |dy| + |dz|) of the octahedron |x| + |y| +
+// |z| = 1, whose lower half (z < 0) is folded onto the square's corners,
+// (x, y) -> ((1 - |y|) sgn x, (1 - |x|) sgn y), kept as (p, q). The harmonic
+// pass needs only the direction of a hit (its list is its bin). Decoding
+// is z = 1 - |p| - |q|, unfolding where z < 0; both steps are well
+// conditioned, so the direction comes back within a few FP32 rounding
+// errors in absolute terms, also near the fold (an encoding by x, y and
+// the sign of z would lose accuracy near z = 0, where z = sqrt(1 - x^2 - y^2)).
+// The approximate reciprocal scales p and q together, and the decoded point
+// is normalised by the reader, so its error does not change the direction
+// beyond that bound.
+__device__ __forceinline__ float2 oct_encode(float dx, float dy, float dz) {
+    const float is = __builtin_amdgcn_rcpf(fabsf(dx) + fabsf(dy) + fabsf(dz));
+    float p = dx * is, q = dy * is;
+    if (dz < 0.f) {
+        const float p0 = p;
+        p = copysignf(1.f - fabsf(q), p0);
+        q = copysignf(1.f - fabsf(p0), q);
+    }
+    return make_float2(p, q);
+}
+// The octahedron point (x, y, z) of a code (a direction, not normalised).
+__device__ __forceinline__ float3 oct_decode(float p, float q) {
+    const float z = 1.f - fabsf(p) - fabsf(q);
+    const float x = z < 0.f ? copysignf(1.f - fabsf(q), p) : p;
+    const float y = z < 0.f ? copysignf(1.f - fabsf(p), q) : q;
+    return make_float3(x, y, z);
+}
 static_assert(kGM * kNW == kItemPrims, "item size");
 
 // A candidate being staged: the point (cell-relative FP32), its piece's shift
@@ -192,9 +222,9 @@ __device__ __forceinline__ void separation(const BinArgs& a, const float4 q, flo
 
 // Records a hit of primary g in bin b (b < 0: none): SWEEP 0 counts it;
 // SWEEP 1 and 2 take the next slot of the bin and write what REC selects:
-// 0 the list entry (FP64 path), 3 the record (dx, dy, dz), 4 the record
-// (dx, dy, dz, w_j); SWEEP 2 drops (but still counts) a hit beyond the end of
-// the bin's predicted region.
+// 0 the list entry (FP64 path), 2 the octahedral code of the direction
+// (p, q) (unit weights), 4 the record (dx, dy, dz, w_j); SWEEP 2 drops (but
+// still counts) a hit beyond the end of the bin's predicted region.
 template <int SWEEP, int REC>
 __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int g, bool hit, int b, uint32_t base_g,
                                         float dx, float dy, float dz, float w, uint32_t entry) {
@@ -207,8 +237,8 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
         if (SWEEP == 2 && pos >= c.end[g * kMaxBins + b]) return;
         // base_g counts pairs of slots (list offsets in units of two)
         const size_t at = 2 * (size_t)base_g + pos;
-        if constexpr (REC == 3) {
-            *reinterpret_cast<float3*>(reinterpret_cast<float*>(a.rec) + 3 * at) = make_float3(dx, dy, dz);
+        if constexpr (REC == 2) {
+            reinterpret_cast<float2*>(a.rec)[at] = oct_encode(dx, dy, dz);
         } else if constexpr (REC == 4) {
             a.rec[at] = make_float4(dx, dy, dz, w);
         } else {
@@ -221,7 +251,7 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
 // (primary, bin); SWEEP 1 writes each hit at base[g] + (running offset of its
 // bin), the offsets having been prepared in cnt; SWEEP 2 does the same inside
 // the predicted regions (their ends in end), and drops (but still counts) the hits
-// beyond a region's end. A hit is written as a list entry, or (REC 3 or 4) as
+// beyond a region's end. A hit is written as a list entry, or (REC 2 or 4) as
 // the record that the FP32 harmonic pass streams.
 //
 // Each thread stages one slot of the next tile: its load is issued before the
@@ -861,7 +891,8 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         off = a.boff[pl * a.nb + b];
     }
     if constexpr (sizeof(T) == 4) {
-        // FP32: the binning pass wrote each hit as (dx, dy, dz, w_j). Two
+        // FP32: the binning pass wrote each hit as (dx, dy, dz, w_j), or
+        // with unit weights as the octahedral code of its direction. Two
         // sets of K records per lane in ping-pong: each half of an iteration
         // first refills the other set with the next K records, then
         // accumulates its own set, loaded one half earlier. The loads are
@@ -871,32 +902,39 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // arithmetic) before. (Conditional loads, or rotating registers,
         // would make every hit wait for the newest load.) Four records per
         // set, eight where the sums alone take more than 128 registers: such
-        // a lane runs at two waves per SIMD, and a set of eight records is a
-        // whole 128-byte line of its list (with four, the two halves of a
-        // line are fetched a set apart, and were measured slower even at
-        // three waves).
+        // a lane runs at two waves per SIMD, and a set of eight 16-byte
+        // records is a whole 128-byte line of its list (with four, the two
+        // halves of a line are fetched a set apart, and were measured slower
+        // even at three waves). With 8-byte codes, sets of sixteen (whole
+        // lines again) were measured slower than sets of eight.
         constexpr int K = AC::NA + AC::NS > 128 ? 8 : 4;
         // an empty list reads the first record of the buffer (not accumulated)
         const size_t roff = n > 0 ? 2 * (size_t)off : 0;  // offsets count pairs of records
         const uint32_t last = n > 0 ? n - 1 : 0;
-        // with UNIT the records are 12 bytes (dx, dy, dz)
+        // with UNIT the records are the 8-byte direction codes (p, q)
         const float4* rec = a.rec + roff;
-        const float3* rec3 = reinterpret_cast<const float3*>(reinterpret_cast<const float*>(a.rec) + 3 * roff);
-        auto load_rec = [&](uint32_t i) {
+        const float2* rec2 = reinterpret_cast<const float2*>(a.rec) + roff;
+        using RecT = std::conditional_t<UNIT, float2, float4>;
+        auto load_rec = [&](uint32_t i) -> RecT {
             if constexpr (UNIT) {
-                const float3 v = rec3[i];
-                return make_float4(v.x, v.y, v.z, 1.f);
+                return rec2[i];
             } else {
                 return rec[i];
             }
         };
-        float4 qa[K], qb[K];
+        RecT qa[K], qb[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) qa[i] = load_rec(min((uint32_t)i, last));
-        auto hit = [&](const float4 q) {
-            const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
-            const float inv = __builtin_amdgcn_rsqf(d2);
-            add_hit<T, LMAX, G, UNIT, SLO>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+        auto hit = [&](const RecT q) {
+            if constexpr (UNIT) {
+                const float3 d = oct_decode(q.x, q.y);
+                const float inv = __builtin_amdgcn_rsqf(d.x * d.x + d.y * d.y + d.z * d.z);
+                add_hit<T, LMAX, G, UNIT, SLO>(acc, d.x * inv, d.y * inv, d.z * inv, 1.f);
+            } else {
+                const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
+                const float inv = __builtin_amdgcn_rsqf(d2);
+                add_hit<T, LMAX, G, UNIT, SLO>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+            }
         };
         for (uint32_t t = 0; t < n; t += 2 * K) {
 #pragma unroll
@@ -1019,24 +1057,30 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
     constexpr int K = 2;
     const size_t roff = n > 0 ? 2 * (size_t)a.boff[pl * a.nb + b] : 0;  // offsets count pairs of records
     const uint32_t last = n > 0 ? n - 1 : 0;
-    // with UNIT the records are 12 bytes (dx, dy, dz)
+    // with UNIT the records are the 8-byte direction codes (p, q)
     const float4* rec = a.rec + roff;
-    const float3* rec3 = reinterpret_cast<const float3*>(reinterpret_cast<const float*>(a.rec) + 3 * roff);
-    auto load_rec = [&](uint32_t i) {
+    const float2* rec2 = reinterpret_cast<const float2*>(a.rec) + roff;
+    using RecT = std::conditional_t<UNIT, float2, float4>;
+    auto load_rec = [&](uint32_t i) -> RecT {
         if constexpr (UNIT) {
-            const float3 v = rec3[i];
-            return make_float4(v.x, v.y, v.z, 1.f);
+            return rec2[i];
         } else {
             return rec[i];
         }
     };
-    float4 qa[K], qb[K];
+    RecT qa[K], qb[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) qa[i] = load_rec(min((uint32_t)(64 * i + lane), last));
-    auto hit = [&](const float4 q) {
-        const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
-        const float inv = __builtin_amdgcn_rsqf(d2);
-        add_hit<float, LMAX, 0, UNIT, SLO>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+    auto hit = [&](const RecT q) {
+        if constexpr (UNIT) {
+            const float3 d = oct_decode(q.x, q.y);
+            const float inv = __builtin_amdgcn_rsqf(d.x * d.x + d.y * d.y + d.z * d.z);
+            add_hit<float, LMAX, 0, UNIT, SLO>(acc, d.x * inv, d.y * inv, d.z * inv, 1.f);
+        } else {
+            const float d2 = q.x * q.x + q.y * q.y + q.z * q.z;
+            const float inv = __builtin_amdgcn_rsqf(d2);
+            add_hit<float, LMAX, 0, UNIT, SLO>(acc, q.x * inv, q.y * inv, q.z * inv, q.w);
+        }
     };
     for (uint32_t t0 = 0; t0 < n; t0 += 128 * K) {
 #pragma unroll
@@ -1169,7 +1213,7 @@ hipError_t launch_pair_bin(const BinArgs& a, hipStream_t s) {
     const int64_t nblk = (nitems + 7) / 8 * 8;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
     if (!a.rec) return launch_bin_rec<0, false>(a, s, nblk, lds);
-    return a.rec3 ? launch_bin_rec<3, false>(a, s, nblk, lds) : launch_bin_rec<4, false>(a, s, nblk, lds);
+    return a.rec_oct ? launch_bin_rec<2, false>(a, s, nblk, lds) : launch_bin_rec<4, false>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s) {
@@ -1178,7 +1222,7 @@ hipError_t launch_pair_fix(const BinArgs& a, hipStream_t s) {
     const int64_t nblk = kFixGrid;
     const size_t lds = pair_bin_lds_bytes(a.npmax);
     if (!a.rec) return launch_bin_rec<0, true>(a, s, nblk, lds);
-    return a.rec3 ? launch_bin_rec<3, true>(a, s, nblk, lds) : launch_bin_rec<4, true>(a, s, nblk, lds);
+    return a.rec_oct ? launch_bin_rec<2, true>(a, s, nblk, lds) : launch_bin_rec<4, true>(a, s, nblk, lds);
 }
 
 hipError_t launch_pair_alm(const AlmArgs& a, int fp64, hipStream_t s) {

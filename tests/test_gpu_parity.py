@@ -279,6 +279,27 @@ def test_lattice_ties_on_bin_edges(torch):
             assert rel_err(got, ref) < TOL[prec], PNAME[prec]
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_lattice_directions_alm(torch, prec):
+    """Integer lattice at lmax 10: every hit lies along an axis, a face or a
+    body diagonal, or another lattice direction, so the FP32 records meet
+    the special cases of their direction code (the poles, the equator z = 0,
+    the fold of the lower half, zero components of either sign). a_lm of
+    every primary against the oracle."""
+    g = np.arange(12, dtype=np.float64)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3) + 0.25
+    box, edges, lmax = 12.0, np.array([0.5, 1.2, 1.6, 2.1, 3.1]), 10
+    res = O.estimate(pos, box, edges, lmax, want_alm=True)
+    mults = O.all_multipoles(lmax, 2)
+    _, npairs, alm, _ = run_gpu(torch, pos, box, edges, lmax, mults, prec, want_alm=True)
+    assert npairs == res.npairs
+    s1 = lmax + 1
+    mask = np.tril(np.ones((s1, s1), dtype=bool))  # m <= l
+    ea = np.abs(alm[..., mask] - res.alm[..., mask]).max() / np.abs(res.alm).max()
+    say(f"  lattice a_lm {PNAME[prec]} rel err {ea:.3e}")
+    assert ea < (1e-12 if prec == T.PREC_FP64 else 1e-5)
+
+
 def test_keep_degenerate_and_literal_flags(torch):
     box, edges, lmax = 50.0, np.array([2.0, 6.0, 10.0]), 3
     pos = C.poisson(600, box, 131)
