@@ -488,7 +488,8 @@ def bench_c5(args):
     plans = {}
 
     def run(prec, steps, warmup):
-        h = T.Handle(box, edges, lmax, precision=prec, grid_refine=args.refine, workspace_limit=160 << 30)
+        # 240 GiB of the 288 GB (one handle at a time): fewer, larger chunks
+        h = T.Handle(box, edges, lmax, precision=prec, grid_refine=args.refine, workspace_limit=240 << 30)
         plans[prec] = tune(h, sizes, pos, w, nd, args)
         h.set_timing(True)
         for _ in range(warmup):
@@ -693,9 +694,9 @@ def main():
 
     print(f"[bench] {args.precision}: {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
-    # 160 GiB of the 288 GB: chunks of 2^21 primaries with their hit lists
+    # 200 GiB of the 288 GB: two chunks of about 4.5M primaries with their hit lists
     h = T.Handle(box, edges, lmax, precision=prec_id, flags=flags, grid_refine=args.refine,
-                 workspace_limit=160 << 30)
+                 workspace_limit=200 << 30)
     plan = tune(h, sizes, pos, None, sizes, args)
     h.set_timing(True)
     rebinned0 = h.rebinned_count()  # the tuner's passes are not counted

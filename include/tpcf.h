@@ -146,7 +146,7 @@ tpcf_status tpcf_build_grid(tpcf_handle h, const double* d_pos, const double* d_
  * the stream once, after the last chunk, to learn whether the hit lists ran
  * out of room (strong clustering), and then runs the pass again with twice
  * the room (which the handle keeps for later calls). TPCF_ERR_ALLOC when the
- * room cannot grow within the workspace limit or 8e9 entries.
+ * room cannot grow within the workspace limit or 16e9 entries.
  */
 tpcf_status tpcf_alm_accumulate(tpcf_handle h);
 

@@ -620,7 +620,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
         double r = 64.0;
         for (int b = 0; b < h->nb; ++b) {
             const double pred = std::min((double)n, n / L3 * h->vol[b]);
-            r += 1.15 * pred + 4.0 * std::sqrt(pred) + 10.0;
+            r += 1.15 * pred + 4.0 * std::sqrt(pred) + 11.0;
         }
         return r;
     };
@@ -628,13 +628,13 @@ tpcf_status plan_chunks(tpcf_handle h) {
     for (int c = 0; c < h->ncat; ++c) room[c] = room_of(h->pt_off[c + 1] - h->pt_off[c]);
     h->hits_per_list = hits / h->nb;
     const double budget = (double)(h->limit / 2);
-    // A chunk takes whole subchunks while its primaries stay within 2^21,
+    // A chunk takes whole subchunks while its primaries stay within 2^23,
     // its operand and predicted list room within the budget, and its list
-    // room within 6.4e9 entries (list offsets are 32-bit counts of entry
-    // pairs: the list regions then get 15 % of slack within 8e9). The room of a subchunk is
+    // room within 12.8e9 entries (list offsets are 32-bit counts of blocks of
+    // four entries: the list regions then get 15 % of slack within 16e9). The room of a subchunk is
     // that of its own catalogue's density, so that a batch of uneven
     // catalogues is not budgeted at the densest one.
-    const int64_t cap = 1 << 21;
+    const int64_t cap = 1 << 23;
     h->chunk_cap = cap;
     h->sub_start.clear();
     h->cat_sub.assign(h->ncat + 1, 0);
@@ -659,7 +659,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
             const int64_t n_s = h->sub_start[s + 1] - h->sub_start[s];
             const double r_s = (double)n_s * room[cat];
             const double b_s = (double)n_s * per_prim + lelem * r_s;
-            if (s > ch.sub_begin && (n_acc + n_s > cap || r_acc + r_s > 6.4e9 || b_acc + b_s > budget)) break;
+            if (s > ch.sub_begin && (n_acc + n_s > cap || r_acc + r_s > 12.8e9 || b_acc + b_s > budget)) break;
             n_acc += n_s;
             r_acc += r_s;
             b_acc += b_s;
@@ -696,7 +696,7 @@ tpcf_status plan_chunks(tpcf_handle h) {
     // regions to their prediction on average, and the 256 regions differ
     // times the growth earlier passes of this handle needed (strong
     // clustering); the chunk sizes keep the prediction
-    h->list_cap = (unsigned long long)std::min(8.0e9, std::max(1.0e6, 1.15 * max_room * h->list_grow));
+    h->list_cap = (unsigned long long)std::min(16.0e9, std::max(1.0e6, 1.15 * max_room * h->list_grow));
     tpcf_status st;
     if ((st = ensure(h, h->d_boff, sizeof(uint32_t) * maxch * h->nb)) != TPCF_OK) return st;
     if ((st = ensure(h, h->d_fix, sizeof(int) * 2 * maxch)) != TPCF_OK) return st;
@@ -749,7 +749,7 @@ tpcf_status pair_chunk(tpcf_handle h, const Chunk& ch) {
     b.rec_oct = (!h->fp64 && h->unit_w && h->lmax <= 10) ? 1 : 0;
     b.pw = h->unit_w ? nullptr : P<float>(h->d_pw);  // null: all weights 1
     b.cursor = P<unsigned long long>(h->d_lcursor);
-    b.capacity = h->list_cap / 2;  // in entry pairs, the unit of the list offsets
+    b.capacity = h->list_cap / 4;  // in blocks of four entries, the unit of the list offsets
     // at least ~64 work items (of at most 16 primaries) per region, so that
     // the regions, taken by the items in turn, fill evenly within the slack
     b.nslots = (int)std::min<int64_t>(kSlots, std::max<int64_t>(1, (ch.p_end - ch.p_begin) / 1024));
@@ -981,7 +981,7 @@ tpcf_status pair_pass(tpcf_handle h, bool contract_now) {
         HIPCHK(hipStreamSynchronize(h->stream));
         h->nfix_total += flag[2];
         if (!flag[0]) return TPCF_OK;
-        const unsigned long long ncap = std::min<unsigned long long>(8000000000ull, h->list_cap * 2);
+        const unsigned long long ncap = std::min<unsigned long long>(16000000000ull, h->list_cap * 2);
         if (attempt == 5 || ncap == h->list_cap) return fail(h, TPCF_ERR_ALLOC, "neighbour list capacity exhausted");
         h->list_cap = ncap;
         h->list_grow = std::min(h->list_grow * 2.0, 64.0);  // kept for the next groups and calls

@@ -90,10 +90,10 @@ struct BinArgs {
     uint32_t* list;          // hit lists of the chunk (list entries), or
     float4* rec;             // hit records (dx, dy, dz, w_j) when not null (FP32 paths)
     int rec_oct;             // 8-byte records, the octahedral code of the direction: unit weights, read by the whole-m FP32 kernels
-    unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each (in entry pairs)
-    unsigned long long capacity;  // room of `list` in entry pairs (two entries or records)
+    unsigned long long* cursor; // [kSlots*16] bump allocators, one region of `list` each (in blocks of four entries)
+    unsigned long long capacity;  // room of `list` in blocks of four entries or records
     int nslots;              // regions the room is split into, one cursor each (<= kSlots)
-    uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists, in entry pairs (every list starts at an even entry)
+    uint32_t* boff;          // [(p_end-p_begin)*nb] offsets of (p, b) lists, in blocks of four entries (every list starts at a multiple of four)
     uint32_t* cnt;           // [(p_end-p_begin)*nb] lengths
     int* overflow;           // [1] set when `list` is too small
     int2* fix;               // fix-up list: (cell, chunk-relative primary) whose predicted bin regions overflowed

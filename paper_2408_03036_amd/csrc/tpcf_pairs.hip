@@ -235,8 +235,8 @@ __device__ __forceinline__ void put_hit(const BinArgs& a, const ItemCtx& c, int 
         // the lists are the same on every run
         const uint32_t pos = atomicAdd(&c.cnt[g * kMaxBins + b], 1u);
         if (SWEEP == 2 && pos >= c.end[g * kMaxBins + b]) return;
-        // base_g counts pairs of slots (list offsets in units of two)
-        const size_t at = 2 * (size_t)base_g + pos;
+        // base_g counts blocks of four slots (the unit of the list offsets)
+        const size_t at = 4 * (size_t)base_g + pos;
         if constexpr (REC == 2) {
             reinterpret_cast<float2*>(a.rec)[at] = oct_encode(dx, dy, dz);
         } else if constexpr (REC == 4) {
@@ -377,8 +377,8 @@ __device__ __forceinline__ void bin_sweep(const BinArgs& a, const ItemCtx& c, co
 // (offset, count) of every (p, b) is published.
 __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]) {
     const int lane = c.lane;
-    // each bin's room is its count rounded up to even: list offsets are
-    // published in units of two slots
+    // each bin's room is its count rounded up to a multiple of four: list
+    // offsets are published in units of four slots
     uint32_t tot[kGM], cl[kGM], ex[kGM];
     uint32_t sum = 0;
 #pragma unroll
@@ -386,7 +386,7 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
         tot[g] = cl[g] = ex[g] = 0;
         if (g >= c.ng) continue;
         const int cn = lane < a.nb ? (int)c.cnt[g * kMaxBins + lane] : 0;
-        const int cv = (cn + 1) & ~1;
+        const int cv = (cn + 3) & ~3;
         int incl = cv;
         for (int o = 1; o < 64; o <<= 1) {
             const int v = __shfl_up(incl, o, 64);
@@ -400,12 +400,12 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
     }
     if (c.ng == 0) return;
     const int slot = c.slot;
-    // cursors, regions and the capacity count units of two slots
+    // cursors, regions and the capacity count units of four slots
     const unsigned long long region = a.capacity / a.nslots;
     unsigned long long b0 = 0;
-    if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)(sum / 2));
+    if (lane == 0) b0 = atomicAdd(a.cursor + slot * 16, (unsigned long long)(sum / 4));
     b0 = __shfl(b0, 0, 64);
-    const bool ok = b0 + sum / 2 <= region;
+    const bool ok = b0 + sum / 4 <= region;
     if (!ok && lane == 0) atomicOr(a.overflow, 1);
     uint32_t run = (uint32_t)(b0 + (unsigned long long)slot * region);
 #pragma unroll
@@ -414,10 +414,10 @@ __device__ void exact_layout(const BinArgs& a, ItemCtx& c, uint32_t (&base)[kGM]
         const int64_t pl = c.cs + c.wave + kNW * g - a.p_begin;
         if (lane < a.nb) {
             a.cnt[pl * a.nb + lane] = ok ? cl[g] : 0u;
-            a.boff[pl * a.nb + lane] = ok ? run + ex[g] / 2 : 0u;
+            a.boff[pl * a.nb + lane] = ok ? run + ex[g] / 4 : 0u;
         }
         if (ok) base[g] = run;
-        run += tot[g] / 2;
+        run += tot[g] / 4;
     }
 }
 
@@ -511,7 +511,8 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             int cap = 0;
             if (lane < a.nb) {
                 const float pred = (float)c.total_full * (float)a.vol[lane] * a.inv_vst;
-                cap = ((int)ceilf(1.15f * pred + 4.0f * sqrtf(pred) + 8.0f) + 1) & ~1;  // even: offsets count pairs
+                // a multiple of four: the offsets count blocks of four slots
+                cap = ((int)ceilf(1.15f * pred + 4.0f * sqrtf(pred) + 8.0f) + 3) & ~3;
             }
             int incl = cap;
             for (int o = 1; o < 64; o <<= 1) {
@@ -521,8 +522,8 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             if (lane <= a.nb) T.capoff[lane] = (uint32_t)(incl - cap);
             const uint32_t captot = (uint32_t)__shfl(incl, 63, 64);
             if (lane == 0) {
-                // in units of two slots (every capacity is even)
-                const unsigned long long sum = (unsigned long long)(captot / 2) * (unsigned)nitem;
+                // in units of four slots (every capacity is a multiple of four)
+                const unsigned long long sum = (unsigned long long)(captot / 4) * (unsigned)nitem;
                 const unsigned long long region = a.capacity / a.nslots;
                 const int slot = c.slot;
                 const unsigned long long b0 = atomicAdd(a.cursor + slot * 16, sum);
@@ -571,7 +572,7 @@ __device__ __forceinline__ void bin_item(const BinArgs& a, ItemCtx& c, Pieces& S
             if (lane < a.nb) {
                 const bool pub = ok && !over;
                 a.cnt[pl * a.nb + lane] = pub ? cv : 0u;
-                a.boff[pl * a.nb + lane] = pub ? ibase + st / 2 : 0u;
+                a.boff[pl * a.nb + lane] = pub ? ibase + st / 4 : 0u;
             }
         }
     }
@@ -909,7 +910,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         // lines again) were measured slower than sets of eight.
         constexpr int K = AC::NA + AC::NS > 128 ? 8 : 4;
         // an empty list reads the first record of the buffer (not accumulated)
-        const size_t roff = n > 0 ? 2 * (size_t)off : 0;  // offsets count pairs of records
+        const size_t roff = n > 0 ? 4 * (size_t)off : 0;  // offsets count blocks of four records
         const uint32_t last = n > 0 ? n - 1 : 0;
         // with UNIT the records are the 8-byte direction codes (p, q)
         const float4* rec = a.rec + roff;
@@ -964,7 +965,7 @@ __global__ void __launch_bounds__(64) k_pair_alm(AlmArgs a) {
         const int64_t cstart = a.pt_off[a.catid[pself]];
         const double4 P64 = a.pd[pself];
         const uint32_t mask = a.g.idx_mask;
-        const uint32_t* lst = n > 0 ? a.list + 2 * (size_t)off : a.list;  // offsets count pairs of entries
+        const uint32_t* lst = n > 0 ? a.list + 4 * (size_t)off : a.list;  // offsets count blocks of four entries
         const uint32_t last = n > 0 ? n - 1 : 0;
         auto entry = [&](uint32_t r) { return lst[min(r, last)]; };
         auto gather = [&](uint32_t r, uint32_t e) { return a.pd[r < n ? cstart + (int64_t)(e & mask) : pself]; };
@@ -1055,7 +1056,7 @@ __global__ void __launch_bounds__(64 * kWaveListWaves) k_pair_alm_wave(AlmArgs a
     // the same ping-pong of unconditional loads as the lane-per-list kernel,
     // over blocks of 64 consecutive records (n is uniform over the wavefront)
     constexpr int K = 2;
-    const size_t roff = n > 0 ? 2 * (size_t)a.boff[pl * a.nb + b] : 0;  // offsets count pairs of records
+    const size_t roff = n > 0 ? 4 * (size_t)a.boff[pl * a.nb + b] : 0;  // offsets count blocks of four records
     const uint32_t last = n > 0 ? n - 1 : 0;
     // with UNIT the records are the 8-byte direction codes (p, q)
     const float4* rec = a.rec + roff;
